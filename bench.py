@@ -1,0 +1,207 @@
+"""Benchmark: batched slot memcpy on one MI355X.
+
+One step = one pass of the data path over one batch: host validation and
+packing of 4,096 memcpy requests, upload, schedule, the fused copy launch
+(piece scan, copy, completion counters) and the fence.  The workload is the
+batched configuration: 8,192 slot windows over a 64 GiB + 64 MiB HBM pool,
+4,096 requests per batch with sizes log-uniform in [256 B, 64 MiB], unaligned
+offsets, disjoint destinations (~22 GB moved, ~44 GB read + written per
+batch).  The pool is filled once with seeded bytes before timing; every step
+uses a different seeded batch.
+
+Printed: one JSON line with the whole-job throughput (algorithmic read +
+write bytes / time), per-step p50/p99, the copy kernel's roofline (event-
+timed on the stream it runs on), HBM traffic from committed rocprofv3
+counters when they still match the kernel source, and the CPU oracle's rate
+on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sched CLASS|tuned|learned]
+       python bench.py --calibrate-copy   (plain-copy kernel for counter scaling)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "achieved HBM GB/s (R+W) for batched slot memcpy/channels vs peak; p99 latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "copy_kernel_batched_traffic.json")
+COPY_SRC = os.path.join(ROOT, "paper_2509_01425_amd", "csrc", "copy.hip")
+
+
+def _src_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per copy launch from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("kernel_source_sha256_16") != _src_hash(COPY_SRC):
+        return None
+    return t
+
+
+def cpu_baseline(batch_descs, target_bytes=12 << 30):
+    """Time the CPU oracle on a bounded sample of one batch: requests taken in
+    a seeded random order until their sizes reach ``target_bytes``, remapped
+    into a host pool (destinations then sources, each request at its original
+    offset modulo 64)."""
+    import oracle
+    g = np.random.default_rng(99)
+    order = g.permutation(len(batch_descs))
+    sizes = batch_descs["size"][order].astype(np.int64)
+    k = int(np.searchsorted(np.cumsum(sizes), target_bytes)) + 1
+    pick = batch_descs[order[:k]]
+    sz = pick["size"].astype(np.int64)
+    dmod = pick["dst_off"].astype(np.int64) % 64
+    smod = pick["src_off"].astype(np.int64) % 64
+    dpos = np.concatenate([[0], np.cumsum(sz + 128)[:-1]]) + dmod
+    dst_len = int(dpos[-1] + sz[-1] + 64)
+    spos = np.concatenate([[0], np.cumsum(sz + 128)[:-1]]) + smod
+    src_len = int(spos[-1] + sz[-1] + 64)
+    dst = np.zeros(dst_len, np.uint8)
+    src = np.ones(src_len, np.uint8)
+    c = oracle.Ctx()
+    _, a = c.register(dst)
+    _, b = c.register(src)
+    d = np.zeros(k, dtype=oracle.DESC_DTYPE)
+    d["dst_slot"], d["src_slot"] = a, b
+    d["dst_off"], d["src_off"], d["size"] = dpos, spos, sz
+    t0 = time.perf_counter()
+    rc, _ = c.memcpy_batch(d)
+    dt = time.perf_counter() - t0
+    assert rc == oracle.OK
+    moved = 2 * int(sz.sum())
+    return {"value": round(moved / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} requests ({int(sz.sum())} bytes) of batch 0, single-threaded "
+                      f"byte-loop oracle, {dt:.2f} s"}
+
+
+def calibrate_copy(n_bytes=4 << 30, reps=3):
+    """Plain aligned copy of a known size, for scaling rocprofv3 counters."""
+    import torch
+    from workloads import device as wd
+    buf = torch.empty(2 * n_bytes, dtype=torch.uint8, device="cuda")
+    for _ in range(reps):
+        wd.ref_copy(buf.data_ptr() + n_bytes, buf.data_ptr(), n_bytes, 1024)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "wl_ref_copy", "bytes_read": n_bytes,
+                      "bytes_written": n_bytes, "launches": reps}), flush=True)
+
+
+def parse_sched(H, text):
+    if text in ("tuned", "learned"):
+        return H.make_sched(64 << 10, 1, 2, H.SCHED_TUNED if text == "tuned" else H.SCHED_LEARNED)
+    rc, s = H.hicr_sched_class(int(text))
+    assert rc == H.OK
+    return s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sched", default="4")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(every run uses exactly one MI355X); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import torch
+    from paper_2509_01425_amd import hicr as H
+    from workloads import device as wd
+    from workloads import memcpy as wm
+
+    stream = torch.cuda.Stream()
+    rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
+    assert rc == H.OK, H.hicr_strerror(rc)
+    pool = torch.empty(wm.B_POOL, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), wm.B_POOL, 7, 0, stream.cuda_stream)
+    bases, sizes = wm.batched_slots()
+    slots = np.empty(len(bases), dtype=np.uint32)
+    for k, (b, s) in enumerate(zip(bases, sizes)):
+        rc, slots[k] = H.hicr_slot_register(ctx, pool.data_ptr() + int(b), int(s), H.MEM_HBM)
+        assert rc == H.OK
+    sched = parse_sched(H, args.sched)
+    batches = []
+    for b in range(args.warmup + args.steps):
+        d = wm.batched(b)
+        d["dst_slot"] = slots[d["dst_slot"]]
+        d["src_slot"] = slots[d["src_slot"]]
+        batches.append(d)
+    moved = [2 * int(d["size"].sum()) for d in batches]
+    torch.cuda.synchronize()
+
+    for b in range(args.warmup):
+        rc, _ = H.hicr_memcpy_batch(ctx, batches[b], sched)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        assert H.hicr_fence(ctx) == H.OK
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    step_s = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        ev[k][0].record(stream)
+        rc, _ = H.hicr_memcpy_batch(ctx, batches[args.warmup + k], sched)
+        ev[k][1].record(stream)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        assert H.hicr_fence(ctx) == H.OK
+        step_s.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+
+    timed_bytes = sum(moved[args.warmup:])
+    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    per_launch = np.array(moved[args.warmup:], dtype=np.float64)
+    achieved = float(np.mean(per_launch / (kern_ms * 1e-3)) / 1e9)
+    traffic = traffic_per_launch()
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
+            "kernel": "hicr::copy_kernel", "avg_launch_ms": round(float(kern_ms.mean()), 4),
+            "algorithmic_bytes_per_launch": int(per_launch.mean())}
+    out = {
+        "metric": METRIC, "value": round(timed_bytes / total / 1e9, 1), "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "batched slot memcpy: 4096 requests/batch, sizes log-uniform "
+                               "256 B..64 MiB, unaligned offsets, disjoint destinations, 8192 "
+                               "slot windows (72 MiB at 8 MiB stride) over a 64 GiB + 64 MiB "
+                               "pool, one fused launch + fence per batch",
+                   "requests_per_batch": 4096, "slots": 8192, "pool_bytes": wm.B_POOL,
+                   "schedule": args.sched, "gb_per_batch_rw": round(float(np.mean(moved)) / 1e9, 3)},
+        "p50_ms": round(float(np.percentile(step_s, 50)) * 1e3, 4),
+        "p99_ms": round(float(np.percentile(step_s, 99)) * 1e3, 4),
+        "roofline": roof,
+    }
+    H.hicr_ctx_destroy(ctx)
+    del pool
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wm.batched(0))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

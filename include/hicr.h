@@ -1,0 +1,156 @@
+/*
+ * hicr.h -- C ABI of the MI355X (gfx950) communication-manager data path.
+ *
+ * Operations follow HiCR (arXiv 2509.01425):
+ *   Sec. 3.1.2  memory spaces            -> HICR_MEM_*
+ *   Sec. 3.1.3  local memory slots       -> hicr_slot_register / _deregister
+ *   Sec. 3.1.4  memcpy(dst, dstOff, src, srcOff, size), rejection of an
+ *               unsupported memory-space pair, asynchronous completion,
+ *               fence on the expected number of incoming and outgoing
+ *               transfers               -> hicr_memcpy, hicr_memcpy_batch,
+ *                                          hicr_fence, hicr_fence_slot,
+ *                                          hicr_slot_counters
+ *   Sec. 4.3    Channels frontend: circular buffers at the consumer, the
+ *               producer waits while the buffer is full, SPSC and MPSC
+ *               (locking / non-locking)  -> hicr_channel_*
+ *
+ * General conventions
+ *   - Every function returns 0 (HICR_OK) or a negative HICR_E* code and never
+ *     throws.  hicr_last_error() gives a human-readable reason for the last
+ *     failure on a context.
+ *   - Pointers named *_dev are device (HBM) addresses; all other pointers are
+ *     host addresses.  "stream" arguments are hipStream_t values passed as
+ *     void*; NULL selects the context's own stream.
+ *   - The caller owns every registered allocation and must keep it alive
+ *     until the slot is deregistered.  The library owns its internal buffers.
+ *   - Transfers are asynchronous: a successful return means the request was
+ *     accepted and enqueued, not that a byte has moved.  Only a fence (or an
+ *     observed counter) guarantees completion and visibility.
+ *   - Within one epoch (between two fences) no byte may be written by two
+ *     requests, or written by one and read by another; such a batch has an
+ *     undefined result, as overlapping C memcpy does.  The library does not
+ *     check this.
+ *   - One context serialises its host calls with a mutex.  GPU code that
+ *     faults or a device-side error surfaces as HICR_EDEVICE at the next fence.
+ */
+#ifndef HICR_H
+#define HICR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define HICR_OK 0
+#define HICR_EINVAL (-1)       /* bad argument                                   */
+#define HICR_ERANGE (-2)       /* offset/size outside the slot                   */
+#define HICR_EBADSLOT (-3)     /* unknown or deregistered slot                   */
+#define HICR_EUNSUPPORTED (-4) /* memory-space pair not supported (Sec. 3.1.4)   */
+#define HICR_EAGAIN (-5)       /* channel full (push) or empty (peek/pop)        */
+#define HICR_ENOMEM (-6)       /* allocation of an internal buffer failed        */
+#define HICR_ETIMEDOUT (-7)    /* expectation not met within the time limit      */
+#define HICR_EHAZARD (-8)      /* reserved for debug hazard checks               */
+#define HICR_EDEVICE (-9)      /* HIP runtime or device-side error               */
+#define HICR_EBUSY (-10)       /* object still has transfers in flight           */
+
+/* Memory spaces (Sec. 3.1.2).  Only HBM -> HBM transfers are supported; a
+ * request touching a host slot is rejected with HICR_EUNSUPPORTED. */
+#define HICR_MEM_HBM 0u
+#define HICR_MEM_HOST 1u
+
+typedef struct hicr_ctx_s *hicr_ctx;
+typedef uint32_t hicr_slot;
+
+/* One memcpy request in the argument order of Sec. 3.1.4 (32 bytes). */
+typedef struct {
+  uint32_t dst_slot;
+  uint32_t src_slot;
+  uint64_t dst_off;
+  uint64_t src_off;
+  uint64_t size;
+} hicr_desc;
+
+/* Copy schedule.  A batch is cut into pieces of at most chunk_bytes; a
+ * request is spread over at least wgs_per_desc pieces (of at least 1 KiB)
+ * when it is large enough; unroll is the number of 16-byte vectors each lane
+ * keeps in flight.  The schedule never changes a byte of the result.
+ * mode: HICR_SCHED_FIXED uses the fields as given; HICR_SCHED_TUNED looks the
+ * batch up in the context's autotuned table; HICR_SCHED_LEARNED lets the
+ * device-resident network pick the class inside the submission. */
+#define HICR_SCHED_FIXED 0u
+#define HICR_SCHED_TUNED 1u
+#define HICR_SCHED_LEARNED 2u
+typedef struct {
+  uint32_t chunk_bytes;  /* multiple of 128, in [128, 1 GiB]  */
+  uint32_t wgs_per_desc; /* 1..64                             */
+  uint32_t unroll;       /* 2 or 4                            */
+  uint32_t mode;
+} hicr_sched;
+
+#define HICR_NUM_CLASSES 12
+/* Class c in [0, 12) -> (chunk, wgs, unroll) with chunk in {4 KiB, 64 KiB,
+ * 1 MiB} (c / 4), wgs in {1, 4} ((c / 2) % 2), unroll in {2, 4} (c % 2). */
+int hicr_sched_class(uint32_t cls, hicr_sched *out);
+
+/* --------------------------------------------------------------- context */
+/* Create a context on HIP device `device`.  `stream` (hipStream_t or NULL)
+ * becomes the default stream; with NULL the context creates its own
+ * non-blocking stream. */
+int hicr_ctx_create(int device, void *stream, hicr_ctx *out);
+/* Fences, then frees every library-owned resource. */
+int hicr_ctx_destroy(hicr_ctx ctx);
+/* Static description of a return code. */
+const char *hicr_strerror(int code);
+/* Copy the last error message of `ctx` into buf (NUL-terminated, at most n). */
+int hicr_last_error(hicr_ctx ctx, char *buf, size_t n);
+/* Default schedule used when hicr_memcpy_batch gets s_or_null == NULL. */
+int hicr_ctx_set_sched(hicr_ctx ctx, const hicr_sched *s);
+
+/* ----------------------------------------------------------------- slots */
+/* Sec. 3.1.3: register the existing allocation [ptr, ptr+size) of memory
+ * space `memspace` as a slot.  For HICR_MEM_HBM the range must lie inside one
+ * device allocation of this context's device.  size == 0 -> HICR_EINVAL.
+ * Slots may alias.  Counters start at zero. */
+int hicr_slot_register(hicr_ctx ctx, void *ptr, uint64_t size, uint32_t memspace,
+                       hicr_slot *out);
+/* Forget a slot.  HICR_EBUSY while any submitted transfer is unfenced. */
+int hicr_slot_deregister(hicr_ctx ctx, hicr_slot slot);
+/* Completed outgoing (sent: slot was the source) and incoming (recv: slot
+ * was the destination) transfers since registration (Sec. 3.1.4).  A
+ * counter is raised only after the transfer's bytes are visible on the
+ * device.  Without a fence the values may lag. */
+int hicr_slot_counters(hicr_ctx ctx, hicr_slot slot, uint64_t *sent, uint64_t *recv);
+
+/* ---------------------------------------------------------------- memcpy */
+/* Sec. 3.1.4 memcpy(dst, dstOff, src, srcOff, size).  Checked at once (slot
+ * ids, bounds without overflow, supported memory-space pair); accepted
+ * requests are queued on the context and launched together, as one fused
+ * batch, at the next fence or batch submission.  size == 0 is a valid
+ * transfer that moves nothing and still counts once. */
+int hicr_memcpy(hicr_ctx ctx, hicr_slot dst, uint64_t dst_off, hicr_slot src, uint64_t src_off,
+                uint64_t size);
+/* Submit n requests as one fused launch on `stream`.  The whole batch is
+ * checked first; on the first invalid request nothing is enqueued, the code
+ * of that request is returned and its index stored in *bad_index_or_null.
+ * `descs` is copied before the call returns.  s_or_null NULL selects the
+ * context default. */
+int hicr_memcpy_batch(hicr_ctx ctx, const hicr_desc *descs, uint64_t n,
+                      const hicr_sched *s_or_null, void *stream, uint64_t *bad_index_or_null);
+/* Sec. 3.1.4 fence: return once every transfer submitted on this context
+ * (any stream) has completed and its bytes and counters are visible.
+ * HICR_EDEVICE if the device reported an error. */
+int hicr_fence(hicr_ctx ctx);
+/* Fence on expected counts (Sec. 3.1.4 "expected number of incoming and
+ * outgoing transfers"): wait until the slot's counters reach at least
+ * (exp_sent, exp_recv).  HICR_ETIMEDOUT when timeout_ns passes first, or at
+ * once when nothing is in flight that could still raise them. */
+int hicr_fence_slot(hicr_ctx ctx, hicr_slot slot, uint64_t exp_sent, uint64_t exp_recv,
+                    uint64_t timeout_ns);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HICR_H */

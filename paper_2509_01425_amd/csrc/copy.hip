@@ -1,0 +1,195 @@
+// copy.hip -- fused batched memcpy for gfx950 (CDNA4).
+//
+// One launch moves a whole batch of memcpy(dst, dstOff, src, srcOff, size)
+// requests (HiCR Sec. 3.1.4) with a persistent grid:
+//   1. every workgroup computes the number of pieces of each request and an
+//      inclusive prefix scan of those counts into LDS (wavefront scans with
+//      __shfl_up, then a cross-wave carry), so the batch becomes one global
+//      index space of pieces;
+//   2. workgroup g takes pieces g, g + G, g + 2G, ...; a 64-ary search over
+//      the LDS table (two ballots for 4,096 requests) finds the request;
+//   3. a piece is copied with 16-byte destination-aligned vector stores and
+//      16-byte loads at whatever alignment the source has (the HSA ABI runs
+//      gfx950 in unaligned-access mode), `unroll` vectors in flight per lane;
+//      the at most 15 bytes before the first and after the last aligned
+//      destination vector are copied byte by byte, so no store ever touches
+//      a byte outside the request;
+//   4. the last workgroup to finish (a device-scope counter) raises the
+//      per-slot sent/received transfer counters of every request, after an
+//      acquire that orders it behind every other workgroup's release.
+#include "internal.h"
+
+namespace hicr {
+
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef v4u v4u_any __attribute__((aligned(1)));  // 16 bytes at any alignment
+// Global address space (1): plain global_load/global_store instead of flat.
+#define GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ v4u load16(uint64_t a) { return *(const GLOBAL v4u_any *)a; }
+
+__device__ __forceinline__ void store16(uint64_t a, v4u v) { *(GLOBAL v4u *)a = v; }
+
+__device__ __forceinline__ void copy_byte(uint64_t d, uint64_t s) {
+  *(GLOBAL unsigned char *)d = *(const GLOBAL unsigned char *)s;
+}
+
+// First index i in [0, n) with ends[i] > q (ends strictly increasing, q <
+// ends[n-1]).  Every lane of the wave returns the same value.
+__device__ __forceinline__ uint32_t find_piece_owner(const uint32_t *ends, uint32_t n, uint32_t q,
+                                                     uint32_t lane) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 64) {
+    uint32_t step = (hi - lo + 63) >> 6;
+    uint32_t idx = lo + (lane + 1) * step - 1;
+    bool gt = (idx >= hi - 1) ? true : (ends[idx] > q);
+    uint64_t m = __ballot(gt);
+    uint32_t f = (uint32_t)__ffsll((unsigned long long)m) - 1;
+    uint32_t nlo = lo + f * step;
+    uint32_t nhi = lo + (f + 1) * step;
+    hi = nhi < hi ? nhi : hi;
+    lo = nlo;
+  }
+  uint32_t idx = lo + lane;
+  bool gt = (idx >= hi - 1) ? true : (ends[idx] > q);
+  uint64_t m = __ballot(gt);
+  return lo + (uint32_t)__ffsll((unsigned long long)m) - 1;
+}
+
+// Copy nv 16-byte vectors: destination d is 16-byte aligned, source s is not
+// necessarily.  Lane t of the workgroup moves vectors t, t + 256, ... with U
+// loads issued before the matching stores.
+template <int U>
+__device__ __forceinline__ void copy_body(uint64_t d, uint64_t s, uint64_t nv, uint32_t tid) {
+  constexpr uint64_t step = (uint64_t)kCopyBlock * U;
+  const uint64_t full = nv - nv % step;
+  uint64_t base = 0;
+  for (; base < full; base += step) {
+    v4u r[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) r[k] = load16(s + (base + tid + (uint64_t)k * kCopyBlock) * 16);
+#pragma unroll
+    for (int k = 0; k < U; k++) store16(d + (base + tid + (uint64_t)k * kCopyBlock) * 16, r[k]);
+  }
+  v4u r[U];
+#pragma unroll
+  for (int k = 0; k < U; k++) {
+    uint64_t idx = base + tid + (uint64_t)k * kCopyBlock;
+    if (idx < nv) r[k] = load16(s + idx * 16);
+  }
+#pragma unroll
+  for (int k = 0; k < U; k++) {
+    uint64_t idx = base + tid + (uint64_t)k * kCopyBlock;
+    if (idx < nv) store16(d + idx * 16, r[k]);
+  }
+}
+
+// Copy destination bytes [lo, hi) from source address s (the source byte of
+// lo).  The head [lo, a0) and tail [a1, hi) are each shorter than 16 bytes.
+__device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s, uint32_t unroll,
+                                           uint32_t tid) {
+  uint64_t a0 = (lo + 15) & ~(uint64_t)15;
+  if (a0 > hi) a0 = hi;
+  uint64_t a1 = hi & ~(uint64_t)15;
+  if (a1 < a0) a1 = a0;
+  if (tid < a0 - lo) copy_byte(lo + tid, s + tid);
+  if (tid >= 64 && tid - 64 < hi - a1) {
+    uint64_t o = (a1 - lo) + (tid - 64);
+    copy_byte(lo + o, s + o);
+  }
+  const uint64_t nv = (a1 - a0) >> 4;
+  if (nv == 0) return;
+  const uint64_t d16 = a0, s16 = s + (a0 - lo);
+  if (unroll >= 4)
+    copy_body<4>(d16, s16, nv, tid);
+  else
+    copy_body<2>(d16, s16, nv, tid);
+}
+
+__global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s0,
+                                                          const DevSched *sched_dev,
+                                                          uint64_t *counters,
+                                                          uint32_t *grid_done) {
+  __shared__ uint32_t ends[kMaxLdsDescs];
+  __shared__ uint32_t wsum[kCopyBlock / 64];
+  __shared__ uint32_t is_last;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  DevSched s = sched_dev ? *sched_dev : s0;
+  const uint32_t n = b.n;
+
+  // 1. pieces per request, then an inclusive block scan in LDS
+  for (uint32_t i = tid; i < n; i += kCopyBlock)
+    ends[i] = (uint32_t)piece_count(b.dst[i], b.size[i], s.chunk, s.wgs);
+  __syncthreads();
+  const uint32_t per = (n + kCopyBlock - 1) / kCopyBlock;
+  const uint32_t k0 = min(tid * per, n), k1 = min(k0 + per, n);
+  uint32_t sum = 0;
+  for (uint32_t k = k0; k < k1; k++) sum += ends[k];
+  uint32_t inc = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += t;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t run = inc - sum;
+  for (uint32_t w = 0; w < wave; w++) run += wsum[w];
+  for (uint32_t k = k0; k < k1; k++) {
+    run += ends[k];
+    ends[k] = run;
+  }
+  __syncthreads();
+  const uint32_t total = n ? ends[n - 1] : 0;
+
+  // 2-3. persistent loop over pieces
+  for (uint32_t q = blockIdx.x; q < total; q += gridDim.x) {
+    uint32_t i = __builtin_amdgcn_readfirstlane(find_piece_owner(ends, n, q, lane));
+    uint32_t j = q - (i ? ends[i - 1] : 0u);
+    const uint64_t dst = b.dst[i], src = b.src[i], size = b.size[i];
+    const uint64_t L = piece_len(dst, size, s.chunk, s.wgs);
+    const uint64_t base = dst & ~(uint64_t)(kLineBytes - 1);
+    uint64_t lo = base + (uint64_t)j * L, hi = lo + L;
+    if (lo < dst) lo = dst;
+    if (hi > dst + size) hi = dst + size;
+    if (lo < hi) copy_range(lo, hi, src + (lo - dst), s.unroll, tid);
+  }
+
+  // 4. completion: release this workgroup's stores, count finished groups
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t prev =
+        __hip_atomic_fetch_add(grid_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == gridDim.x - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    for (uint32_t i = tid; i < n; i += kCopyBlock) {
+      const uint64_t sp = b.slots[i];
+      const uint64_t dslot = sp & 0xffffffffull, sslot = sp >> 32;
+      __hip_atomic_fetch_add(&counters[2 * sslot], 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&counters[2 * dslot + 1], 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid == 0) __hip_atomic_store(grid_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_copy(const DevBatch &b, DevSched s, const DevSched *sched_dev,
+                       uint64_t *counters, uint32_t *grid_done, uint32_t grid,
+                       hipStream_t stream) {
+  if (b.n > kMaxLdsDescs || grid == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(kCopyBlock), 0, stream, b, s, sched_dev,
+                     counters, grid_done);
+  return hipGetLastError();
+}
+
+int copy_occupancy(int *wgs_per_cu) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, copy_kernel, kCopyBlock,
+                                                            0);
+}
+
+}  // namespace hicr

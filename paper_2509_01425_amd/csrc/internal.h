@@ -1,0 +1,63 @@
+// internal.h -- structures shared by the host runtime and the gfx950 kernels
+// of the copy engine.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hicr {
+
+constexpr int kCopyBlock = 256;         // threads per copy workgroup (4 waves)
+constexpr uint32_t kMaxLdsDescs = 4096; // requests per launch (16 KiB LDS piece table)
+constexpr uint32_t kLineBytes = 128;    // interior piece boundaries are line aligned
+constexpr uint32_t kMinSplit = 1024;    // never split a request below 1 KiB pieces
+
+// Device-side batch: structure of arrays, uploaded in one copy.  Addresses
+// are already resolved from (slot, offset) on the host.
+struct DevBatch {
+  const uint64_t *dst;   // [n] destination byte address
+  const uint64_t *src;   // [n] source byte address
+  const uint64_t *size;  // [n] bytes
+  const uint64_t *slots; // [n] dst_slot | (uint64_t)src_slot << 32
+  uint32_t n;
+};
+
+// Schedule as the kernel sees it (a device word when a device-side selector
+// chose it).
+struct DevSched {
+  uint32_t chunk, wgs, unroll, cls;
+};
+
+// Piece length for one request under (chunk, wgs): pieces start at line
+// boundaries of the destination (except the first), so a piece never shares
+// a 16-byte store with its neighbour inside one request.
+__host__ __device__ inline uint64_t piece_len(uint64_t dst, uint64_t size, uint32_t chunk,
+                                              uint32_t wgs) {
+  uint64_t span = dst + size - (dst & ~(uint64_t)(kLineBytes - 1));
+  uint64_t L = chunk;
+  if (wgs > 1 && span < (uint64_t)wgs * chunk) {
+    uint64_t per = (span + wgs - 1) / wgs;
+    per = (per + kLineBytes - 1) & ~(uint64_t)(kLineBytes - 1);
+    if (per < kMinSplit) per = kMinSplit;
+    if (per < L) L = per;
+  }
+  return L;
+}
+
+__host__ __device__ inline uint64_t piece_count(uint64_t dst, uint64_t size, uint32_t chunk,
+                                                uint32_t wgs) {
+  if (size == 0) return 1;  // a zero-byte request still completes (and counts) once
+  uint64_t span = dst + size - (dst & ~(uint64_t)(kLineBytes - 1));
+  uint64_t L = piece_len(dst, size, chunk, wgs);
+  return (span + L - 1) / L;
+}
+
+// Launch the fused copy kernel over one sub-batch (n <= kMaxLdsDescs).
+// sched_dev, when not null, overrides `s` with a device-resident choice.
+hipError_t launch_copy(const DevBatch &b, DevSched s, const DevSched *sched_dev,
+                       uint64_t *counters, uint32_t *grid_done, uint32_t grid,
+                       hipStream_t stream);
+// Workgroups of the copy kernel that one CU holds at once.
+int copy_occupancy(int *wgs_per_cu);
+
+}  // namespace hicr

@@ -1,0 +1,457 @@
+// runtime.cpp -- host side of the communication-manager data path: context,
+// slot table, request validation, fused-batch submission and fences.
+//
+// Slots (HiCR Sec. 3.1.3) live in a host table; requests are validated on
+// the host and resolved to absolute device addresses, packed as a structure
+// of arrays into pinned staging, uploaded with one asynchronous copy and
+// moved by one fused copy launch per (at most 4,096-request) sub-batch.
+// Per-slot counters live in device memory and are raised by the copy kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hicr.h"
+#include "internal.h"
+#include "runtime.h"
+
+using namespace hicr;
+
+namespace {
+
+constexpr uint32_t kChunks[3] = {4u << 10, 64u << 10, 1u << 20};
+constexpr uint32_t kWgs[2] = {1, 4};
+constexpr uint32_t kUnroll[2] = {2, 4};
+
+}  // namespace
+
+namespace hicr {
+
+int fail(hicr_ctx c, int code, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(hicr_ctx c, hipError_t e, const char *what) {
+  return fail(c, HICR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_sched(hicr_ctx c, const hicr_sched &s) {
+  if (s.chunk_bytes < kLineBytes || s.chunk_bytes > (1u << 30) || s.chunk_bytes % kLineBytes)
+    return fail(c, HICR_EINVAL, "chunk_bytes %u: must be a multiple of 128 in [128, 1 GiB]",
+                s.chunk_bytes);
+  if (s.wgs_per_desc < 1 || s.wgs_per_desc > 64)
+    return fail(c, HICR_EINVAL, "wgs_per_desc %u outside [1, 64]", s.wgs_per_desc);
+  if (s.unroll != 2 && s.unroll != 4) return fail(c, HICR_EINVAL, "unroll %u not 2 or 4", s.unroll);
+  return HICR_OK;
+}
+
+int check_desc(hicr_ctx c, const hicr_desc &d) {
+  if (d.dst_slot >= c->slots.size() || !c->slots[d.dst_slot].live) return HICR_EBADSLOT;
+  if (d.src_slot >= c->slots.size() || !c->slots[d.src_slot].live) return HICR_EBADSLOT;
+  const Slot &ds = c->slots[d.dst_slot], &ss = c->slots[d.src_slot];
+  if (d.dst_off > ds.size || d.size > ds.size - d.dst_off) return HICR_ERANGE;
+  if (d.src_off > ss.size || d.size > ss.size - d.src_off) return HICR_ERANGE;
+  if (ds.space != HICR_MEM_HBM || ss.space != HICR_MEM_HBM) return HICR_EUNSUPPORTED;
+  return HICR_OK;
+}
+
+bool any_inflight(hicr_ctx c) {
+  for (Sub &s : c->subs) {
+    if (!s.inflight) continue;
+    if (hipEventQuery(s.ev) == hipSuccess)
+      s.inflight = false;
+    else
+      return true;
+  }
+  return false;
+}
+
+int wait_sub(hicr_ctx c, Sub &s) {
+  if (!s.inflight) return HICR_OK;
+  hipError_t e = hipEventSynchronize(s.ev);
+  s.inflight = false;
+  if (e != hipSuccess) return hip_fail(c, e, "waiting for a batch");
+  return HICR_OK;
+}
+
+int wait_all(hicr_ctx c) {
+  int rc = HICR_OK;
+  for (Sub &s : c->subs) {
+    int r = wait_sub(c, s);
+    if (r != HICR_OK) rc = r;
+  }
+  int r = wait_extra(c);
+  if (r != HICR_OK) rc = r;
+  return rc;
+}
+
+static int ensure_capacity(hicr_ctx c, Sub &s, uint64_t n) {
+  if (n <= s.cap) return HICR_OK;
+  uint64_t cap = std::max<uint64_t>(n, std::max<uint64_t>(2 * s.cap, 4096));
+  if (s.h) (void)hipHostFree(s.h);
+  if (s.d) (void)hipFree(s.d);
+  s.h = nullptr;
+  s.d = nullptr;
+  s.cap = 0;
+  hipError_t e = hipHostMalloc(&s.h, cap * 32, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(c, HICR_ENOMEM, "pinned staging of %llu requests", (unsigned long long)cap);
+  e = hipMalloc(&s.d, cap * 32);
+  if (e != hipSuccess) return fail(c, HICR_ENOMEM, "device batch buffer of %llu requests", (unsigned long long)cap);
+  s.cap = cap;
+  return HICR_OK;
+}
+
+int ensure_counter_capacity(hicr_ctx c, uint32_t nslots) {
+  if (nslots <= c->counter_cap) return HICR_OK;
+  int rc = wait_all(c);
+  if (rc != HICR_OK) return rc;
+  uint32_t cap = std::max<uint32_t>(nslots, 2 * c->counter_cap);
+  uint64_t *nc = nullptr;
+  hipError_t e = hipMalloc(&nc, (size_t)cap * 16);
+  if (e != hipSuccess) return fail(c, HICR_ENOMEM, "counter table of %u slots", cap);
+  e = hipMemset(nc, 0, (size_t)cap * 16);
+  if (e == hipSuccess && c->counter_cap)
+    e = hipMemcpy(nc, c->d_counters, (size_t)c->counter_cap * 16, hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(nc);
+    return hip_fail(c, e, "growing the counter table");
+  }
+  (void)hipFree(c->d_counters);
+  c->d_counters = nc;
+  c->counter_cap = cap;
+  return HICR_OK;
+}
+
+// Validate, pack and launch n requests as one submission.
+int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
+           const DevSched *sched_dev, hipStream_t stream, uint64_t *bad) {
+  for (uint64_t i = 0; i < n; i++) {
+    int rc = check_desc(c, d[i]);
+    if (rc != HICR_OK) {
+      if (bad) *bad = i;
+      return fail(c, rc, "request %llu rejected", (unsigned long long)i);
+    }
+  }
+  if (n == 0) return HICR_OK;
+  // Choose the submission buffer (round robin; wait if still in flight).
+  Sub &s = c->subs[c->next_sub];
+  c->next_sub = (c->next_sub + 1) % kNumSubs;
+  int rc = wait_sub(c, s);
+  if (rc != HICR_OK) return rc;
+  rc = ensure_capacity(c, s, n);
+  if (rc != HICR_OK) return rc;
+  uint64_t *h = static_cast<uint64_t *>(s.h);
+  uint64_t *hd = h, *hs = h + n, *hz = h + 2 * n, *hp = h + 3 * n;
+  for (uint64_t i = 0; i < n; i++) {
+    hd[i] = c->slots[d[i].dst_slot].base + d[i].dst_off;
+    hs[i] = c->slots[d[i].src_slot].base + d[i].src_off;
+    hz[i] = d[i].size;
+    hp[i] = (uint64_t)d[i].dst_slot | ((uint64_t)d[i].src_slot << 32);
+  }
+  hipError_t e = hipMemcpyAsync(s.d, s.h, n * 32, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "uploading a batch");
+  const uint64_t *dd = static_cast<const uint64_t *>(s.d);
+  DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
+  // With a device-side choice the host does not know the chunk; bound the
+  // piece count with the smallest chunk of any class.
+  const uint32_t bound_chunk = sched_dev ? kChunks[0] : sched.chunk_bytes;
+  const uint32_t bound_wgs = sched_dev ? 64u : sched.wgs_per_desc;
+  const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)c->occ;
+  uint64_t i0 = 0;
+  while (i0 < n) {
+    uint64_t i1 = i0, pieces = 0;
+    while (i1 < n && i1 - i0 < kMaxLdsDescs) {
+      uint64_t p = piece_count(hd[i1], hz[i1], bound_chunk, bound_wgs);
+      if (i1 > i0 && pieces + p >= (1ull << 31)) break;
+      pieces += p;
+      i1++;
+    }
+    if (pieces >= (1ull << 31))
+      return fail(c, HICR_EINVAL, "request %llu needs more than 2^31 pieces",
+                  (unsigned long long)i0);
+    DevBatch b{dd + i0, dd + n + i0, dd + 2 * n + i0, dd + 3 * n + i0, (uint32_t)(i1 - i0)};
+    uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(pieces, 1), cap_grid);
+    e = launch_copy(b, ds, sched_dev, c->d_counters, s.grid_done, grid, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
+    i0 = i1;
+  }
+  e = hipEventRecord(s.ev, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "recording a batch event");
+  s.inflight = true;
+  return HICR_OK;
+}
+
+int flush_pending(hicr_ctx c) {
+  if (c->pending.empty()) return HICR_OK;
+  std::vector<hicr_desc> p;
+  p.swap(c->pending);
+  uint64_t bad = 0;
+  return submit(c, p.data(), p.size(), c->def_sched, nullptr, c->stream, &bad);
+}
+
+}  // namespace hicr
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+int hicr_sched_class(uint32_t cls, hicr_sched *out) {
+  if (!out || cls >= HICR_NUM_CLASSES) return HICR_EINVAL;
+  out->chunk_bytes = kChunks[cls / 4];
+  out->wgs_per_desc = kWgs[(cls / 2) % 2];
+  out->unroll = kUnroll[cls % 2];
+  out->mode = HICR_SCHED_FIXED;
+  return HICR_OK;
+}
+
+const char *hicr_strerror(int code) {
+  switch (code) {
+    case HICR_OK: return "ok";
+    case HICR_EINVAL: return "invalid argument";
+    case HICR_ERANGE: return "offset or size outside the slot";
+    case HICR_EBADSLOT: return "unknown or deregistered slot";
+    case HICR_EUNSUPPORTED: return "memory-space pair not supported";
+    case HICR_EAGAIN: return "channel full or empty; try again";
+    case HICR_ENOMEM: return "out of memory";
+    case HICR_ETIMEDOUT: return "timed out";
+    case HICR_EHAZARD: return "conflicting requests in one epoch";
+    case HICR_EDEVICE: return "device or HIP runtime error";
+    case HICR_EBUSY: return "transfers still in flight";
+    default: return "unknown error";
+  }
+}
+
+int hicr_last_error(hicr_ctx c, char *buf, size_t n) {
+  if (!c || !buf || n == 0) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  snprintf(buf, n, "%s", c->err.c_str());
+  return HICR_OK;
+}
+
+int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
+  if (!out) return HICR_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HICR_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return HICR_EDEVICE;
+  hicr_ctx c = new (std::nothrow) hicr_ctx_s();
+  if (!c) return HICR_ENOMEM;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return HICR_EDEVICE;
+  }
+  c->n_cu = prop.multiProcessorCount;
+  if (copy_occupancy(&c->occ) != 0 || c->occ < 1) c->occ = 1;
+  if (stream) {
+    c->stream = static_cast<hipStream_t>(stream);
+    c->own_stream = false;
+  } else if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return HICR_EDEVICE;
+  } else {
+    c->own_stream = true;
+  }
+  bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipMalloc(&c->d_words, kNumSubs * 64) == hipSuccess;
+  ok = ok && hipMemset(c->d_words, 0, kNumSubs * 64) == hipSuccess;
+  ok = ok && hipHostMalloc(&c->h_read, 64, hipHostMallocDefault) == hipSuccess;
+  for (int i = 0; ok && i < kNumSubs; i++) {
+    ok = hipEventCreateWithFlags(&c->subs[i].ev, hipEventDisableTiming) == hipSuccess;
+    c->subs[i].grid_done = reinterpret_cast<uint32_t *>(c->d_words + 64 * i);
+  }
+  c->def_sched = hicr_sched{64u << 10, 1, 2, HICR_SCHED_FIXED};
+  if (!ok || ensure_counter_capacity(c, 1024) != HICR_OK) {
+    hicr_ctx_destroy(c);
+    return HICR_EDEVICE;
+  }
+  *out = c;
+  return HICR_OK;
+}
+
+int hicr_ctx_destroy(hicr_ctx c) {
+  if (!c) return HICR_EINVAL;
+  (void)hipSetDevice(c->device);
+  wait_all(c);
+  destroy_extra(c);
+  for (Sub &s : c->subs) {
+    if (s.h) (void)hipHostFree(s.h);
+    if (s.d) (void)hipFree(s.d);
+    if (s.ev) (void)hipEventDestroy(s.ev);
+  }
+  if (c->d_counters) (void)hipFree(c->d_counters);
+  if (c->d_words) (void)hipFree(c->d_words);
+  if (c->h_read) (void)hipHostFree(c->h_read);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return HICR_OK;
+}
+
+int hicr_ctx_set_sched(hicr_ctx c, const hicr_sched *s) {
+  if (!c || !s) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (s->mode != HICR_SCHED_FIXED) return fail(c, HICR_EINVAL, "default schedule must be fixed");
+  int rc = check_sched(c, *s);
+  if (rc == HICR_OK) c->def_sched = *s;
+  return rc;
+}
+
+int hicr_slot_register(hicr_ctx c, void *ptr, uint64_t size, uint32_t memspace, hicr_slot *out) {
+  if (!c || !out) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  if (!ptr) return fail(c, HICR_EINVAL, "null address");
+  if (size == 0) return fail(c, HICR_EINVAL, "a slot needs a non-zero size");
+  if (memspace != HICR_MEM_HBM && memspace != HICR_MEM_HOST)
+    return fail(c, HICR_EINVAL, "unknown memory space %u", memspace);
+  if (memspace == HICR_MEM_HBM) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != c->device) {
+      (void)hipGetLastError();
+      return fail(c, HICR_EINVAL, "address is not device memory of device %d", c->device);
+    }
+    hipDeviceptr_t base = nullptr;
+    size_t alloc = 0;
+    if (hipMemGetAddressRange(&base, &alloc, ptr) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, HICR_EINVAL, "address outside every device allocation");
+    }
+    uint64_t b = reinterpret_cast<uint64_t>(base), p = reinterpret_cast<uint64_t>(ptr);
+    if (p - b > alloc || size > alloc - (p - b))
+      return fail(c, HICR_ERANGE, "slot extends past the end of its allocation");
+  }
+  if (c->slots.size() >= 0xffffffffull) return fail(c, HICR_ENOMEM, "slot ids exhausted");
+  int rc = ensure_counter_capacity(c, (uint32_t)c->slots.size() + 1);
+  if (rc != HICR_OK) return rc;
+  Slot s;
+  s.base = reinterpret_cast<uint64_t>(ptr);
+  s.size = size;
+  s.space = memspace;
+  s.live = true;
+  c->slots.push_back(s);
+  *out = (hicr_slot)(c->slots.size() - 1);
+  return HICR_OK;
+}
+
+int hicr_slot_deregister(hicr_ctx c, hicr_slot slot) {
+  if (!c) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
+  for (const hicr_desc &d : c->pending)
+    if (d.dst_slot == slot || d.src_slot == slot)
+      return fail(c, HICR_EBUSY, "slot has unsubmitted transfers; fence first");
+  (void)hipSetDevice(c->device);
+  if (any_inflight(c) || extra_inflight(c))
+    return fail(c, HICR_EBUSY, "transfers in flight; fence first");
+  c->slots[slot].live = false;
+  return HICR_OK;
+}
+
+int hicr_slot_counters(hicr_ctx c, hicr_slot slot, uint64_t *sent, uint64_t *recv) {
+  if (!c) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipMemcpyAsync(c->h_read, c->d_counters + 2 * slot, 16, hipMemcpyDeviceToHost,
+                                c->aux);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->aux);
+  if (e != hipSuccess) return hip_fail(c, e, "reading counters");
+  if (sent) *sent = c->h_read[0];
+  if (recv) *recv = c->h_read[1];
+  return HICR_OK;
+}
+
+int hicr_memcpy(hicr_ctx c, hicr_slot dst, uint64_t dst_off, hicr_slot src, uint64_t src_off,
+                uint64_t size) {
+  if (!c) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  hicr_desc d{dst, src, dst_off, src_off, size};
+  int rc = check_desc(c, d);
+  if (rc != HICR_OK) return fail(c, rc, "memcpy rejected");
+  c->pending.push_back(d);
+  if (c->pending.size() >= kMaxLdsDescs) {
+    (void)hipSetDevice(c->device);
+    return flush_pending(c);
+  }
+  return HICR_OK;
+}
+
+int hicr_memcpy_batch(hicr_ctx c, const hicr_desc *descs, uint64_t n, const hicr_sched *s,
+                      void *stream, uint64_t *bad) {
+  if (!c || (n && !descs)) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  hicr_sched sched = s ? *s : c->def_sched;
+  const DevSched *sched_dev = nullptr;
+  if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
+    int rc = choose_sched(c, descs, n, sched.mode, &sched, &sched_dev,
+                          stream ? static_cast<hipStream_t>(stream) : c->stream);
+    if (rc != HICR_OK) return rc;
+  } else if (sched.mode != HICR_SCHED_FIXED) {
+    return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
+  }
+  int rc = check_sched(c, sched);
+  if (rc != HICR_OK) return rc;
+  rc = flush_pending(c);
+  if (rc != HICR_OK) return rc;
+  return submit(c, descs, n, sched, sched_dev,
+                stream ? static_cast<hipStream_t>(stream) : c->stream, bad);
+}
+
+int hicr_fence(hicr_ctx c) {
+  if (!c) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  int rc = flush_pending(c);
+  int r2 = wait_all(c);
+  return rc != HICR_OK ? rc : r2;
+}
+
+int hicr_fence_slot(hicr_ctx c, hicr_slot slot, uint64_t exp_sent, uint64_t exp_recv,
+                    uint64_t timeout_ns) {
+  if (!c) return HICR_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
+    (void)hipSetDevice(c->device);
+    int rc = flush_pending(c);
+    if (rc != HICR_OK) return rc;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    bool busy;
+    {
+      std::lock_guard<std::mutex> g(c->mu);
+      busy = any_inflight(c) || extra_inflight(c);
+    }
+    uint64_t s = 0, r = 0;
+    int rc = hicr_slot_counters(c, slot, &s, &r);
+    if (rc != HICR_OK) return rc;
+    if (s >= exp_sent && r >= exp_recv) return HICR_OK;
+    if (!busy) return fail(c, HICR_ETIMEDOUT, "expected counts cannot be reached");
+    auto dt = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                  std::chrono::steady_clock::now() - t0).count();
+    if ((uint64_t)dt >= timeout_ns) return fail(c, HICR_ETIMEDOUT, "fence_slot timed out");
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+}  // extern "C"

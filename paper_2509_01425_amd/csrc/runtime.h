@@ -1,0 +1,80 @@
+// runtime.h -- the host context shared by the runtime's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hicr.h"
+#include "internal.h"
+
+namespace hicr {
+
+struct Slot {
+  uint64_t base = 0;
+  uint64_t size = 0;
+  uint32_t space = 0;
+  bool live = false;
+};
+
+// One submission buffer: pinned staging, its device copy, the event that
+// marks the end of the submission, and the finished-workgroup counter.
+struct Sub {
+  void *h = nullptr;
+  void *d = nullptr;
+  uint64_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool inflight = false;
+  uint32_t *grid_done = nullptr;
+};
+
+constexpr int kNumSubs = 4;
+
+struct SchedState;  // autotuned table and device-resident network (sched.cpp)
+
+}  // namespace hicr
+
+struct hicr_ctx_s {
+  std::mutex mu;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipStream_t aux = nullptr;  // counter reads, never waits on `stream`
+  int n_cu = 1;
+  int occ = 1;  // copy workgroups per CU
+  std::vector<hicr::Slot> slots;
+  uint64_t *d_counters = nullptr;  // [slot] = {sent, recv}
+  uint32_t counter_cap = 0;
+  char *d_words = nullptr;  // small device words (grid_done per submission)
+  uint64_t *h_read = nullptr;  // pinned read-back buffer
+  hicr::Sub subs[hicr::kNumSubs];
+  int next_sub = 0;
+  std::vector<hicr_desc> pending;
+  hicr_sched def_sched{};
+  hicr::SchedState *sched = nullptr;
+  std::string err;
+};
+
+namespace hicr {
+
+int fail(hicr_ctx c, int code, const char *fmt, ...);
+int hip_fail(hicr_ctx c, hipError_t e, const char *what);
+int check_desc(hicr_ctx c, const hicr_desc &d);
+int check_sched(hicr_ctx c, const hicr_sched &s);
+bool any_inflight(hicr_ctx c);
+int wait_all(hicr_ctx c);
+int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
+           const DevSched *sched_dev, hipStream_t stream, uint64_t *bad);
+int flush_pending(hicr_ctx c);
+int ensure_counter_capacity(hicr_ctx c, uint32_t nslots);
+
+// Hooks implemented by the schedule selector (sched.cpp).
+int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out,
+                 const DevSched **sched_dev, hipStream_t stream);
+int wait_extra(hicr_ctx c);
+bool extra_inflight(hicr_ctx c);
+void destroy_extra(hicr_ctx c);
+
+}  // namespace hicr

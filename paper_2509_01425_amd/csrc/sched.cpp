@@ -1,0 +1,20 @@
+// sched.cpp -- schedule selection for a batch (fixed / autotuned / learned).
+#include "runtime.h"
+
+namespace hicr {
+
+struct SchedState {};
+
+int choose_sched(hicr_ctx c, const hicr_desc *, uint64_t, uint32_t mode, hicr_sched *,
+                 const DevSched **, hipStream_t) {
+  return fail(c, HICR_EINVAL, "schedule mode %u is not available on this context", mode);
+}
+
+int wait_extra(hicr_ctx) { return HICR_OK; }
+bool extra_inflight(hicr_ctx) { return false; }
+void destroy_extra(hicr_ctx c) {
+  delete c->sched;
+  c->sched = nullptr;
+}
+
+}  // namespace hicr

@@ -1,0 +1,161 @@
+"""Thin ctypes binding of libhicr.so (argument marshalling only).
+
+Function names match the C ABI in include/hicr.h.  Every function returns the
+C return code first, followed by any output values.  Device buffers are
+passed as integer addresses (e.g. ``tensor.data_ptr()``); streams as integer
+hipStream_t handles (e.g. ``torch.cuda.current_stream().cuda_stream``) or 0
+for the context's own stream.
+
+The library must have been built (``paper_2509_01425_amd.build``); there is no
+fallback: importing this module on a machine without the built library
+raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhicr.so")
+
+OK = 0
+EINVAL = -1
+ERANGE = -2
+EBADSLOT = -3
+EUNSUPPORTED = -4
+EAGAIN = -5
+ENOMEM = -6
+ETIMEDOUT = -7
+EHAZARD = -8
+EDEVICE = -9
+EBUSY = -10
+
+MEM_HBM = 0
+MEM_HOST = 1
+
+SCHED_FIXED = 0
+SCHED_TUNED = 1
+SCHED_LEARNED = 2
+NUM_CLASSES = 12
+
+DESC_DTYPE = np.dtype(
+    [("dst_slot", "<u4"), ("src_slot", "<u4"), ("dst_off", "<u8"),
+     ("src_off", "<u8"), ("size", "<u8")], align=True)
+
+
+class hicr_sched(ctypes.Structure):
+    _fields_ = [("chunk_bytes", ctypes.c_uint32), ("wgs_per_desc", ctypes.c_uint32),
+                ("unroll", ctypes.c_uint32), ("mode", ctypes.c_uint32)]
+
+
+_u32, _u64, _vp, _int = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+_pu32, _pu64, _pvp = ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_vp)
+
+_SIGNATURES = {
+    "hicr_sched_class": (_int, [_u32, ctypes.POINTER(hicr_sched)]),
+    "hicr_ctx_create": (_int, [_int, _vp, _pvp]),
+    "hicr_ctx_destroy": (_int, [_vp]),
+    "hicr_strerror": (ctypes.c_char_p, [_int]),
+    "hicr_last_error": (_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
+    "hicr_ctx_set_sched": (_int, [_vp, ctypes.POINTER(hicr_sched)]),
+    "hicr_slot_register": (_int, [_vp, _vp, _u64, _u32, _pu32]),
+    "hicr_slot_deregister": (_int, [_vp, _u32]),
+    "hicr_slot_counters": (_int, [_vp, _u32, _pu64, _pu64]),
+    "hicr_memcpy": (_int, [_vp, _u32, _u64, _u32, _u64, _u64]),
+    "hicr_memcpy_batch": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_sched), _vp, _pu64]),
+    "hicr_fence": (_int, [_vp]),
+    "hicr_fence_slot": (_int, [_vp, _u32, _u64, _u64, _u64]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2509_01425_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+# ------------------------------------------------------------------ calls
+
+def hicr_sched_class(cls: int):
+    s = hicr_sched()
+    rc = lib().hicr_sched_class(cls, ctypes.byref(s))
+    return rc, s
+
+
+def make_sched(chunk_bytes: int, wgs_per_desc: int, unroll: int, mode: int = SCHED_FIXED):
+    return hicr_sched(chunk_bytes, wgs_per_desc, unroll, mode)
+
+
+def hicr_ctx_create(device: int = 0, stream: int = 0):
+    out = _vp()
+    rc = lib().hicr_ctx_create(device, stream or None, ctypes.byref(out))
+    return rc, out.value
+
+
+def hicr_ctx_destroy(ctx) -> int:
+    return lib().hicr_ctx_destroy(ctx)
+
+
+def hicr_strerror(code: int) -> str:
+    return lib().hicr_strerror(code).decode()
+
+
+def hicr_last_error(ctx) -> str:
+    buf = ctypes.create_string_buffer(512)
+    lib().hicr_last_error(ctx, buf, 512)
+    return buf.value.decode()
+
+
+def hicr_ctx_set_sched(ctx, sched: hicr_sched) -> int:
+    return lib().hicr_ctx_set_sched(ctx, ctypes.byref(sched))
+
+
+def hicr_slot_register(ctx, ptr: int, size: int, memspace: int = MEM_HBM):
+    out = _u32()
+    rc = lib().hicr_slot_register(ctx, ptr, size, memspace, ctypes.byref(out))
+    return rc, out.value
+
+
+def hicr_slot_deregister(ctx, slot: int) -> int:
+    return lib().hicr_slot_deregister(ctx, slot)
+
+
+def hicr_slot_counters(ctx, slot: int):
+    s, r = _u64(), _u64()
+    rc = lib().hicr_slot_counters(ctx, slot, ctypes.byref(s), ctypes.byref(r))
+    return rc, s.value, r.value
+
+
+def hicr_memcpy(ctx, dst: int, dst_off: int, src: int, src_off: int, size: int) -> int:
+    return lib().hicr_memcpy(ctx, dst, dst_off, src, src_off, size)
+
+
+def hicr_memcpy_batch(ctx, descs: np.ndarray, sched=None, stream: int = 0):
+    d = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+    bad = _u64(0)
+    rc = lib().hicr_memcpy_batch(ctx, d.ctypes.data if d.size else None, d.size,
+                                 ctypes.byref(sched) if sched is not None else None,
+                                 stream or None, ctypes.byref(bad))
+    return rc, bad.value
+
+
+def hicr_fence(ctx) -> int:
+    return lib().hicr_fence(ctx)
+
+
+def hicr_fence_slot(ctx, slot: int, exp_sent: int, exp_recv: int, timeout_ns: int) -> int:
+    return lib().hicr_fence_slot(ctx, slot, exp_sent, exp_recv, timeout_ns)

@@ -1,0 +1,55 @@
+"""Helpers that turn oracle results into expected device contents.
+
+Expected values come only from the CPU oracle (``oracle``) applied to inputs
+drawn by ``workloads``; nothing here reads the GPU library's results except
+the arrays handed in for comparison.
+"""
+import numpy as np
+
+import oracle
+from workloads.content import content
+
+
+def abs_ranges(descs, bases):
+    """Absolute (dst, src, size) of every request given slot base offsets."""
+    dabs = np.asarray(bases, dtype=np.uint64)[descs["dst_slot"]] + descs["dst_off"]
+    sabs = np.asarray(bases, dtype=np.uint64)[descs["src_slot"]] + descs["src_off"]
+    return dabs.astype(np.int64), sabs.astype(np.int64), descs["size"].astype(np.int64)
+
+
+def expected_window(dabs, sabs, size, w0, w1, seed):
+    """Bytes [w0, w1) of a pool filled under ``seed`` after one hazard-free
+    batch: the oracle's memcpy applied, in index order, to every request whose
+    destination meets the window (clipped to it), each reading its source from
+    the content as it was at the start of the epoch."""
+    win = content(seed, w0, w1 - w0)
+    c = oracle.Ctx()
+    rc, wslot = c.register(win)
+    assert rc == oracle.OK
+    hit = np.nonzero((dabs < w1) & (dabs + size > w0) & (size > 0))[0]
+    for j in hit:
+        x0 = max(int(dabs[j]), w0)
+        x1 = min(int(dabs[j] + size[j]), w1)
+        src = content(seed, int(sabs[j]) + (x0 - int(dabs[j])), x1 - x0)
+        rc, sslot = c.register(src)
+        assert rc == oracle.OK
+        assert c.memcpy(wslot, x0 - w0, sslot, 0, x1 - x0) == oracle.OK
+    return win
+
+
+def oracle_counters(descs, n_slots):
+    """Per-slot (sent, recv) after one batch, from the oracle's counter rule."""
+    c = oracle.Ctx()
+    dummy = np.zeros(1, np.uint8)
+    # Slots of size 2^62 at one shared address: only the counter effect is
+    # used (count_batch moves no bytes), so bounds never bind.
+    for _ in range(n_slots):
+        rc, _s = c.register_raw(dummy.ctypes.data, 1 << 62)
+        assert rc == oracle.OK
+    rc, bad = c.count_batch(descs)
+    assert rc == oracle.OK, (rc, bad)
+    out = np.zeros((n_slots, 2), dtype=np.uint64)
+    for k in range(n_slots):
+        _, s, r = c.counters(k)
+        out[k] = (s, r)
+    return out

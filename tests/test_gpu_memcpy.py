@@ -1,0 +1,289 @@
+"""GPU parity of the fused batched memcpy against the CPU oracle.
+
+Every expected byte and counter comes from ``oracle`` on inputs drawn by
+``workloads``; the comparison is bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import abs_ranges, expected_window, oracle_counters
+from workloads import memcpy as wm
+from workloads.content import content
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2509_01425_amd import hicr as H
+    from workloads import device as wd
+    assert torch.cuda.is_available()
+    rc, ctx = H.hicr_ctx_create(0, 0)
+    assert rc == H.OK, H.hicr_strerror(rc)
+    yield torch, H, wd, ctx
+    assert H.hicr_ctx_destroy(ctx) == H.OK
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _register_pool(H, ctx, pool, bases, sizes):
+    slots = []
+    for b, s in zip(bases, sizes):
+        rc, sl = H.hicr_slot_register(ctx, pool.data_ptr() + int(b), int(s), H.MEM_HBM)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        slots.append(sl)
+    return np.array(slots, dtype=np.uint32)
+
+
+def _remap(descs, slots):
+    d = descs.copy()
+    d["dst_slot"] = slots[descs["dst_slot"]]
+    d["src_slot"] = slots[descs["src_slot"]]
+    return d
+
+
+def test_device_fill_matches_generator(env):
+    torch, H, wd, ctx = env
+    for n, first in [(1, 0), (7, 8), (4096 + 5, 0), (1 << 20, 64), (3 << 20, 1 << 30)]:
+        _say("fill", n, first)
+        buf = torch.empty(n, dtype=torch.uint8, device="cuda")
+        wd.fill(buf.data_ptr(), n, 77, first)
+        torch.cuda.synchronize()
+        assert np.array_equal(buf.cpu().numpy(), content(77, first, n))
+
+
+@pytest.mark.parametrize("cls", list(range(12)))
+def test_tiny_all_schedules(env, cls):
+    """The tiny workload (64 packed slots, 256 requests) under every one of
+    the 12 schedule classes: whole pool and every counter equal the oracle."""
+    torch, H, wd, ctx = env
+    bases, sizes, pool_len, descs, _ = wm.tiny(0)
+    seed = 1000 + cls
+    _say("tiny class", cls)
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), pool_len, seed)
+    torch.cuda.synchronize()
+    slots = _register_pool(H, ctx, pool, bases, sizes)
+    rc, sched = H.hicr_sched_class(cls)
+    rc, bad = H.hicr_memcpy_batch(ctx, _remap(descs, slots), sched)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK
+    got = pool.cpu().numpy()
+    # oracle on the host
+    host = content(seed, 0, pool_len)
+    oc = oracle.Ctx()
+    for b, s in zip(bases, sizes):
+        assert oc.register(host, offset=int(b), size=int(s))[0] == oracle.OK
+    assert oc.hazard_check(descs)[0] == oracle.OK
+    assert oc.memcpy_batch(descs)[0] == oracle.OK
+    assert np.array_equal(got, host), np.nonzero(got != host)[0][:10]
+    for k, sl in enumerate(slots):
+        rc, s, r = H.hicr_slot_counters(ctx, int(sl))
+        assert (rc, s, r) == oc.counters(k)
+    assert H.hicr_fence(ctx) == H.OK
+    for sl in slots:
+        assert H.hicr_slot_deregister(ctx, int(sl)) == H.OK
+
+
+def test_alignment_grid_and_edges(env):
+    """Every (dst mod 16, src mod 16) pair, sizes around 16/128/1K/64K piece
+    edges, zero-size requests, one request spanning many pieces, under the
+    smallest and largest chunk."""
+    torch, H, wd, ctx = env
+    g = np.random.default_rng(42)
+    sizes = [0, 1, 2, 15, 16, 17, 31, 33, 127, 128, 129, 1023, 1025, 4095, 4097,
+             65535, 65537, 200_003]
+    reqs = []
+    for da in range(16):
+        for sa in range(16):
+            reqs.append((da, sa, int(g.choice(sizes))))
+    reqs.append((3, 9, (8 << 20) + 13))   # one large request: many pieces
+    # lay requests out in one pool: destinations first, then sources
+    cur = 0
+    d_at, s_at = [], []
+    for da, sa, n in reqs:
+        cur = ((cur + 63) // 64) * 64 + da
+        d_at.append(cur)
+        cur += n + 16
+    for da, sa, n in reqs:
+        cur = ((cur + 63) // 64) * 64 + sa
+        s_at.append(cur)
+        cur += n + 16
+    pool_len = cur + 64
+    for cls in (0, 11):
+        _say("alignment grid class", cls)
+        seed = 500 + cls
+        pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+        wd.fill(pool.data_ptr(), pool_len, seed)
+        torch.cuda.synchronize()
+        rc, slot = H.hicr_slot_register(ctx, pool.data_ptr(), pool_len, H.MEM_HBM)
+        assert rc == H.OK
+        d = np.zeros(len(reqs), dtype=H.DESC_DTYPE)
+        for i, (r, da, sa) in enumerate(zip(reqs, d_at, s_at)):
+            d[i] = (slot, slot, da, sa, r[2])
+        rc, sched = H.hicr_sched_class(cls)
+        assert H.hicr_memcpy_batch(ctx, d, sched)[0] == H.OK
+        assert H.hicr_fence(ctx) == H.OK
+        host = content(seed, 0, pool_len)
+        oc = oracle.Ctx()
+        _, os_ = oc.register(host)
+        od = d.copy()
+        od["dst_slot"] = os_
+        od["src_slot"] = os_
+        assert oc.hazard_check(od)[0] == oracle.OK
+        assert oc.memcpy_batch(od)[0] == oracle.OK
+        got = pool.cpu().numpy()
+        assert np.array_equal(got, host), np.nonzero(got != host)[0][:10]
+        assert H.hicr_slot_counters(ctx, slot) == (H.OK, len(reqs), len(reqs))
+        assert H.hicr_slot_deregister(ctx, slot) == H.OK
+
+
+def test_many_requests_split_launches(env):
+    """10,001 small requests: more than one 4,096-request launch."""
+    torch, H, wd, ctx = env
+    g = np.random.default_rng(3)
+    n = 10_001
+    sz = g.integers(0, 300, n)
+    dst = np.concatenate([[0], np.cumsum(sz + 5)[:-1]]) + 3
+    src_base = int(dst[-1] + sz[-1] + 4096)
+    src = src_base + np.concatenate([[0], np.cumsum(sz + 1)[:-1]])
+    pool_len = int(src[-1] + sz[-1] + 64)
+    seed = 9
+    _say("split launches", n)
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), pool_len, seed)
+    torch.cuda.synchronize()
+    rc, a = H.hicr_slot_register(ctx, pool.data_ptr(), src_base, H.MEM_HBM)
+    rc2, b = H.hicr_slot_register(ctx, pool.data_ptr() + src_base, pool_len - src_base, H.MEM_HBM)
+    assert rc == rc2 == H.OK
+    d = np.zeros(n, dtype=H.DESC_DTYPE)
+    d["dst_slot"], d["src_slot"] = a, b
+    d["dst_off"], d["src_off"], d["size"] = dst, src - src_base, sz
+    rc, sched = H.hicr_sched_class(5)
+    assert H.hicr_memcpy_batch(ctx, d, sched)[0] == H.OK
+    assert H.hicr_fence(ctx) == H.OK
+    host = content(seed, 0, pool_len)
+    oc = oracle.Ctx()
+    oa = oc.register(host, offset=0, size=src_base)[1]
+    ob = oc.register(host, offset=src_base, size=pool_len - src_base)[1]
+    od = d.copy()
+    od["dst_slot"], od["src_slot"] = oa, ob
+    assert oc.memcpy_batch(od)[0] == oracle.OK
+    assert np.array_equal(pool.cpu().numpy(), host)
+    assert H.hicr_slot_counters(ctx, a) == (H.OK, 0, n)
+    assert H.hicr_slot_counters(ctx, b) == (H.OK, n, 0)
+
+
+def test_single_memcpy_broadcast_and_fence_slot(env):
+    """One message copied to many destinations with single memcpy calls and
+    one fence (the paper's broadcast example, on one memory space)."""
+    torch, H, wd, ctx = env
+    msg_len, ndst = 1000, 37
+    _say("broadcast")
+    msg = torch.empty(msg_len + 5, dtype=torch.uint8, device="cuda")
+    wd.fill(msg.data_ptr(), msg_len + 5, 5)
+    dsts = torch.zeros(ndst, msg_len + 3, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    rc, sm = H.hicr_slot_register(ctx, msg.data_ptr() + 5, msg_len, H.MEM_HBM)
+    assert rc == H.OK
+    dslots = []
+    for k in range(ndst):
+        rc, s = H.hicr_slot_register(ctx, dsts[k].data_ptr() + 3, msg_len, H.MEM_HBM)
+        assert rc == H.OK
+        dslots.append(s)
+        assert H.hicr_memcpy(ctx, s, 0, sm, 0, msg_len) == H.OK
+    assert H.hicr_fence_slot(ctx, sm, ndst, 0, 10**9) == H.OK
+    assert H.hicr_fence(ctx) == H.OK
+    want = content(5, 5, msg_len)
+    got = dsts.cpu().numpy()
+    for k in range(ndst):
+        assert np.array_equal(got[k, 3:], want) and not got[k, :3].any()
+    assert H.hicr_slot_counters(ctx, sm) == (H.OK, ndst, 0)
+    assert H.hicr_fence_slot(ctx, sm, ndst + 1, 0, 10**6) == H.ETIMEDOUT
+    assert H.hicr_fence_slot(ctx, dslots[0], 0, 1, 10**6) == H.OK
+
+
+def test_rejections_enqueue_nothing(env):
+    torch, H, wd, ctx = env
+    _say("rejections")
+    a = torch.arange(64, dtype=torch.uint8, device="cuda")
+    b = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    h = torch.zeros(64, dtype=torch.uint8).pin_memory()
+    torch.cuda.synchronize()
+    assert H.hicr_slot_register(ctx, a.data_ptr(), 0, H.MEM_HBM)[0] == H.EINVAL
+    assert H.hicr_slot_register(ctx, 0, 8, H.MEM_HBM)[0] == H.EINVAL
+    assert H.hicr_slot_register(ctx, h.data_ptr(), 64, H.MEM_HBM)[0] == H.EINVAL
+    assert H.hicr_slot_register(ctx, a.data_ptr(), 64, 9)[0] == H.EINVAL
+    _, sa = H.hicr_slot_register(ctx, a.data_ptr(), 64, H.MEM_HBM)
+    _, sb = H.hicr_slot_register(ctx, b.data_ptr(), 64, H.MEM_HBM)
+    rc, sh = H.hicr_slot_register(ctx, h.data_ptr(), 64, H.MEM_HOST)
+    assert rc == H.OK
+    d = np.zeros(3, dtype=H.DESC_DTYPE)
+    d[:] = [(sb, sa, 0, 0, 8), (sb, sa, 8, 60, 8), (sb, sa, 16, 0, 4)]
+    assert H.hicr_memcpy_batch(ctx, d) == (H.ERANGE, 1)
+    d[1] = (sh, sa, 0, 0, 4)
+    assert H.hicr_memcpy_batch(ctx, d) == (H.EUNSUPPORTED, 1)
+    d[1] = (sb, 12345, 0, 0, 4)
+    assert H.hicr_memcpy_batch(ctx, d) == (H.EBADSLOT, 1)
+    assert H.hicr_memcpy(ctx, sb, 0, sa, 2**64 - 1, 2) == H.ERANGE
+    assert H.hicr_fence(ctx) == H.OK
+    assert not b.cpu().numpy().any()
+    assert H.hicr_slot_counters(ctx, sa) == (H.OK, 0, 0)
+    bad = H.make_sched(100, 1, 2)
+    assert H.hicr_memcpy_batch(ctx, d[:1], bad)[0] == H.EINVAL
+    # deregistration waits for the fence
+    d[1] = (sb, sa, 8, 8, 8)
+    assert H.hicr_memcpy_batch(ctx, d)[0] == H.OK
+    assert H.hicr_fence(ctx) == H.OK
+    assert H.hicr_slot_deregister(ctx, sa) == H.OK
+    assert H.hicr_slot_counters(ctx, sa)[0] == H.EBADSLOT
+    assert H.hicr_memcpy(ctx, sb, 0, sa, 0, 1) == H.EBADSLOT
+
+
+def test_batched_full_size_sampled(env):
+    """One batch of the measured configuration (8,192 slot windows over a
+    64 GiB + 64 MiB pool, 4,096 requests, ~22 GB) in the launch configuration
+    the benchmark times; sampled destination windows (with margins) are
+    compared with the oracle, every slot counter with the oracle's."""
+    torch, H, wd, ctx = env
+    seed = 4242
+    bases, sizes = wm.batched_slots()
+    _say("batched full size: alloc", wm.B_POOL)
+    pool = torch.empty(wm.B_POOL, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), wm.B_POOL, seed)
+    torch.cuda.synchronize()
+    slots = _register_pool(H, ctx, pool, bases, sizes)
+    descs = wm.batched(0)
+    rc, sched = H.hicr_sched_class(8)
+    _say("batched full size: submit")
+    rc, bad = H.hicr_memcpy_batch(ctx, _remap(descs, slots), sched)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK
+    dabs, sabs, size = abs_ranges(descs, bases)
+    g = np.random.default_rng(1)
+    order = np.argsort(size)
+    pick = np.unique(np.concatenate([order[:6], order[-4:], g.choice(len(size), 30, replace=False)]))
+    for j in pick:
+        w0 = max(0, int(dabs[j]) - 64)
+        w1 = min(wm.B_POOL, int(dabs[j] + size[j]) + 64)
+        want = expected_window(dabs, sabs, size, w0, w1, seed)
+        got = pool[w0:w1].cpu().numpy()
+        assert np.array_equal(got, want), (j, np.nonzero(got != want)[0][:8])
+    # untouched space: random windows
+    for w0 in g.integers(0, wm.B_POOL - 4096, 20):
+        w0 = int(w0)
+        want = expected_window(dabs, sabs, size, w0, w0 + 4096, seed)
+        assert np.array_equal(pool[w0:w0 + 4096].cpu().numpy(), want)
+    exp = oracle_counters(descs, len(slots))
+    for k in range(0, len(slots), 97):
+        assert H.hicr_slot_counters(ctx, int(slots[k]))[1:] == tuple(int(x) for x in exp[k])
+    tot_s = sum(H.hicr_slot_counters(ctx, int(s))[1] for s in slots[:512])
+    assert tot_s == int(exp[:512, 0].sum())
+    for s in slots:
+        assert H.hicr_slot_deregister(ctx, int(s)) == H.OK
+    del pool
+    torch.cuda.empty_cache()
