@@ -99,6 +99,45 @@ def calibrate_copy(n_bytes=4 << 30, reps=3):
                       "bytes_written": n_bytes, "launches": reps}), flush=True)
 
 
+def channel_rig(torch, H, ctx, plan, mpsc_mode, seed, stream=0):
+    """Allocate, fill and register everything a channel plan needs and create
+    its device-endpoint channels; returns the pump's stream list and buffers."""
+    from workloads import device as wd
+    S = plan.n_streams
+    src = torch.empty(S * plan.src_bytes, dtype=torch.uint8, device="cuda")
+    wd.fill(src.data_ptr(), src.numel(), seed, 0, stream)
+    sb = plan.stream_bytes().astype(np.int64)
+    out_off = np.concatenate([[0], np.cumsum(sb)[:-1]]).astype(np.int64)
+    out = torch.zeros(int(sb.sum()) + 64, dtype=torch.uint8, device="cuda")
+    rings_per = [1] * plan.n_spsc + [1 if mpsc_mode == H.CH_MPSC_LOCK else plan.K] * plan.n_mpsc
+    n_rings = sum(rings_per)
+    payload = torch.empty(n_rings * plan.P, dtype=torch.uint8, device="cuda")
+    entries = torch.zeros(n_rings * plan.E, dtype=torch.int64, device="cuda")
+    chans = []
+    r0 = 0
+    for c, nr in enumerate(rings_per):
+        _, ps = H.hicr_slot_register(ctx, payload.data_ptr() + r0 * plan.P, nr * plan.P)
+        _, es = H.hicr_slot_register(ctx, entries.data_ptr() + r0 * plan.E * 8, nr * plan.E * 8)
+        spsc = c < plan.n_spsc
+        cfg = H.make_channel_cfg(H.CH_VAR, H.CH_SPSC if spsc else mpsc_mode,
+                                 1 if spsc else plan.K, H.CH_DEVICE, ps, es,
+                                 capacity=plan.P, entries=plan.E)
+        rc, ch = H.hicr_channel_create(ctx, cfg)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        chans.append(ch)
+        r0 += nr
+    streams = []
+    for s in range(S):
+        rc, ss = H.hicr_slot_register(ctx, src.data_ptr() + s * plan.src_bytes, plan.src_bytes)
+        assert rc == H.OK
+        rc, os_ = H.hicr_slot_register(ctx, out.data_ptr() + int(out_off[s]), max(int(sb[s]), 1))
+        assert rc == H.OK
+        streams.append((chans[int(plan.stream_channel[s])], int(plan.stream_producer[s]), ss, os_,
+                        int(plan.msg_begin[s]), int(plan.msg_begin[s + 1] - plan.msg_begin[s])))
+    return {"streams": streams, "src": src, "out": out, "out_off": out_off, "stream_bytes": sb,
+            "payload": payload, "entries": entries, "channels": chans}
+
+
 def parse_sched(H, text):
     if text in ("tuned", "learned"):
         return H.make_sched(64 << 10, 1, 2, H.SCHED_TUNED if text == "tuned" else H.SCHED_LEARNED)

@@ -150,6 +150,113 @@ int hicr_fence(hicr_ctx ctx);
 int hicr_fence_slot(hicr_ctx ctx, hicr_slot slot, uint64_t exp_sent, uint64_t exp_recv,
                     uint64_t timeout_ns);
 
+
+/* -------------------------------------------------------------- channels */
+/* Sec. 4.3 Channels: circular buffers pre-allocated at the consumer.  The
+ * caller registers the payload ring(s) and the entry ring(s) as HBM slots;
+ * the library owns the coordination counters.  Counters are monotone, so a
+ * ring of C tokens holds C tokens (no wasted slot).
+ *
+ *   kind      HICR_CH_FIXED: tokens of token_bytes; capacity = C tokens;
+ *                            `entries` ignored (one entry per token).
+ *             HICR_CH_VAR:   messages of 0..capacity bytes; capacity = P
+ *                            payload bytes per ring; `entries` = E messages;
+ *                            a message crossing the ring end continues at
+ *                            the ring start.
+ *   mode      HICR_CH_SPSC (producers = 1), HICR_CH_MPSC_LOCK (one shared
+ *             ring; exclusive access for the room check and reservation, so
+ *             the ring holds one total order), HICR_CH_MPSC_NOLOCK (one ring
+ *             per producer, more memory, no exclusive access).
+ *   endpoints HICR_CH_HOST: producer and consumer call the host API below;
+ *             HICR_CH_DEVICE: producer and consumer are GPU workgroups of
+ *             hicr_channel_pump (the host API then returns HICR_EINVAL).
+ *   payload   slot of at least rings * ring_bytes bytes (ring r at r * ring_bytes);
+ *   entries   slot of at least rings * E * 8 bytes, 8-byte aligned
+ *             (rings = producers for MPSC_NOLOCK, else 1; ring_bytes = C * T or P).
+ * The channel starts empty.  A channel must not outlive its context. */
+#define HICR_CH_FIXED 0u
+#define HICR_CH_VAR 1u
+#define HICR_CH_SPSC 0u
+#define HICR_CH_MPSC_LOCK 1u
+#define HICR_CH_MPSC_NOLOCK 2u
+#define HICR_CH_HOST 0u
+#define HICR_CH_DEVICE 1u
+#define HICR_CH_MAX_PRODUCERS 64u
+
+typedef struct hicr_channel_s *hicr_channel;
+typedef struct {
+  uint32_t kind;
+  uint32_t mode;
+  uint32_t producers;
+  uint32_t endpoints;
+  uint64_t token_bytes; /* FIXED: T                     */
+  uint64_t capacity;    /* FIXED: C tokens; VAR: P bytes */
+  uint64_t entries;     /* VAR: E messages per ring      */
+  hicr_slot payload;
+  hicr_slot entries_slot;
+} hicr_channel_cfg;
+
+int hicr_channel_create(hicr_ctx ctx, const hicr_channel_cfg *cfg, hicr_channel *out);
+/* Waits for the channel's pushes in flight, then frees it. */
+int hicr_channel_destroy(hicr_channel ch);
+/* Producer `producer` pushes `count` tokens (FIXED; all or nothing) or one
+ * message of `count` bytes (VAR) read from slot `src` at `src_off`.  The
+ * producer may not push while the ring lacks room: HICR_EAGAIN (retry after
+ * the consumer pops).  count > C (FIXED) or > P (VAR): HICR_EINVAL.  The
+ * payload moves asynchronously on the context stream; the consumer sees the
+ * message once the device has published it. */
+int hicr_channel_push(hicr_channel ch, uint32_t producer, hicr_slot src, uint64_t src_off,
+                      uint64_t count);
+/* The i-th oldest published message of ring `ring` (the producer index for
+ * MPSC_NOLOCK, else 0): its byte offset inside the payload slot, its size
+ * and its producer.  HICR_EAGAIN if fewer than i + 1 messages are visible. */
+int hicr_channel_peek(hicr_channel ch, uint32_t ring, uint64_t i, uint64_t *payload_off,
+                      uint64_t *bytes, uint32_t *producer);
+/* Consume the n oldest messages of `ring`: the notification that frees their
+ * room.  Reads of their bytes must be complete (e.g. a hicr_memcpy from the
+ * payload slot followed by hicr_fence) before the call.  HICR_EAGAIN if fewer
+ * than n are visible. */
+int hicr_channel_pop(hicr_channel ch, uint32_t ring, uint64_t n);
+/* Messages and bytes visible to the consumer in `ring`. */
+int hicr_channel_depth(hicr_channel ch, uint32_t ring, uint64_t *msgs, uint64_t *bytes);
+
+/* One producer stream of a pump: `n_msgs` messages, message j read from slot
+ * `src` at msg_src_off[first_msg + j] with msg_size[first_msg + j] bytes,
+ * pushed by producer `producer` of `channel`; the consumer appends the
+ * stream's messages, in order, to slot `out` from offset 0. */
+typedef struct {
+  hicr_channel channel;
+  uint32_t producer;
+  hicr_slot src;
+  hicr_slot out;
+  uint32_t pad;
+  uint64_t first_msg;
+  uint64_t n_msgs;
+} hicr_stream;
+
+typedef struct {
+  const uint64_t *msg_src_off; /* host array [n_msgs]                              */
+  const uint64_t *msg_size;    /* host array [n_msgs]; FIXED channels: token_bytes */
+  uint64_t n_msgs;
+  uint32_t *trace_dev;   /* optional device array: for every consumed message, its
+                            stream index; channels in order of first appearance in
+                            the stream list, each in the order its consumer took them */
+  uint64_t *ts_dev;      /* optional device array [2 * n_msgs]: publish time, then
+                            consume time of every message (100 MHz device clock)    */
+  uint64_t timeout_ns;   /* a wait that sees no progress for this long ends the
+                            pump with HICR_ETIMEDOUT at the next fence (0: 10 s)    */
+} hicr_pump_io;
+
+/* Run every stream through its device-endpoint channel in one persistent
+ * launch on `stream`: one GPU wave per producer stream, one workgroup per
+ * consumer.  Validated on the host (slots, ranges, sizes, one stream per
+ * (channel, producer)); HICR_EINVAL if the launch would not fit on the device
+ * at once.  Asynchronous; hicr_fence reports a time-out or abort. */
+int hicr_channel_pump(hicr_ctx ctx, const hicr_stream *streams, uint32_t n_streams,
+                      const hicr_pump_io *io, void *stream);
+/* Ask running pumps of this context to stop (they end at their next wait). */
+int hicr_channel_abort(hicr_ctx ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,527 @@
+// channel.cpp -- host side of the ring channels (HiCR Sec. 4.3): creation,
+// the non-blocking host API (push / peek / pop / depth) and the persistent
+// device pump.
+//
+// Host-endpoint channels keep their coordination counters in host-coherent
+// pinned memory: a push enqueues push_kernel, which copies the payload into
+// the HBM ring and then publishes the new message counter with a
+// system-scope release; the host consumer reads that counter, and its pop
+// stores the released counters that the host producer checks for room.
+// Device-endpoint channels keep their counters in HBM and are driven by
+// pump_kernel.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "chan.h"
+#include "runtime.h"
+
+using namespace hicr;
+
+struct hicr_channel_s {
+  hicr_ctx ctx = nullptr;
+  hicr_channel_cfg cfg{};
+  uint32_t n_rings = 1;
+  uint64_t P = 0, E = 0;
+  uint64_t payload_base = 0, entries_base = 0;
+  RingCoord *coord_host = nullptr;  // host view (host endpoints)
+  RingCoord *coord_dev = nullptr;   // device view
+  bool broken = false;
+  struct RingHost {
+    uint64_t tm = 0, tb = 0;  // producer side: enqueued
+    uint64_t hm = 0, hb = 0;  // consumer side: released
+    std::vector<uint64_t> ent;
+  };
+  std::vector<RingHost> rh;
+};
+
+namespace {
+
+uint64_t entry_size(uint64_t e) { return e & kEntrySizeMask; }
+
+int check_hbm_slot(hicr_ctx c, hicr_slot s, uint64_t need, const char *what) {
+  if (s >= c->slots.size() || !c->slots[s].live) return fail(c, HICR_EBADSLOT, "%s: bad slot", what);
+  if (c->slots[s].space != HICR_MEM_HBM)
+    return fail(c, HICR_EUNSUPPORTED, "%s: slot is not in HBM", what);
+  if (c->slots[s].size < need)
+    return fail(c, HICR_ERANGE, "%s: slot holds %llu bytes, needs %llu", what,
+                (unsigned long long)c->slots[s].size, (unsigned long long)need);
+  return HICR_OK;
+}
+
+bool registered(hicr_ctx c, hicr_channel ch) {
+  return std::find(c->channels.begin(), c->channels.end(), ch) != c->channels.end();
+}
+
+// A device buffer [p, p + bytes) must lie inside one allocation of the device.
+int check_dev_range(hicr_ctx c, const void *p, uint64_t bytes, const char *what) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      attr.device != c->device) {
+    (void)hipGetLastError();
+    return fail(c, HICR_EINVAL, "%s is not device memory", what);
+  }
+  hipDeviceptr_t base = nullptr;
+  size_t alloc = 0;
+  if (hipMemGetAddressRange(&base, &alloc, const_cast<void *>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, HICR_EINVAL, "%s outside every allocation", what);
+  }
+  uint64_t b = reinterpret_cast<uint64_t>(base), q = reinterpret_cast<uint64_t>(p);
+  if (q - b > alloc || bytes > alloc - (q - b))
+    return fail(c, HICR_ERANGE, "%s is smaller than %llu bytes", what, (unsigned long long)bytes);
+  return HICR_OK;
+}
+
+DevRing dev_ring(const hicr_channel_s *ch, uint32_t r) {
+  return DevRing{ch->payload_base + r * ch->P, ch->P, ch->entries_base + r * ch->E * 8, ch->E,
+                 reinterpret_cast<uint64_t>(ch->coord_dev + r)};
+}
+
+void free_channel(hicr_channel ch) {
+  if (ch->cfg.endpoints == HICR_CH_HOST) {
+    if (ch->coord_host) (void)hipHostFree(ch->coord_host);
+  } else if (ch->coord_dev) {
+    (void)hipFree(ch->coord_dev);
+  }
+  delete ch;
+}
+
+}  // namespace
+
+namespace hicr {
+
+int wait_extra(hicr_ctx c) {
+  int rc = HICR_OK;
+  if (c->push_pending) {
+    hipError_t e = hipEventSynchronize(c->push_ev);
+    c->push_pending = false;
+    if (e != hipSuccess) rc = hip_fail(c, e, "waiting for channel pushes");
+  }
+  for (Extra &x : c->extra) {
+    hipError_t e = hipEventSynchronize(x.ev);
+    if (e != hipSuccess) {
+      rc = hip_fail(c, e, "waiting for a pump");
+    } else if (x.pump) {
+      const uint32_t *err = static_cast<const uint32_t *>(x.h_buf);
+      if (err[0] & kErrCorrupt) rc = fail(c, HICR_EDEVICE, "a channel pump read a malformed entry");
+      else if (err[0] & kErrTimeout) rc = fail(c, HICR_ETIMEDOUT, "a channel pump made no progress");
+      else if (err[1]) rc = fail(c, HICR_EDEVICE, "a channel pump was aborted");
+      if (err[0] || err[1])
+        for (hicr_channel ch : x.chans) ch->broken = true;
+    }
+    {
+      std::lock_guard<std::mutex> g(c->abort_mu);
+      c->abort_words.erase(std::remove(c->abort_words.begin(), c->abort_words.end(), x.abort_word),
+                           c->abort_words.end());
+    }
+    (void)hipEventDestroy(x.ev);
+    if (x.d_buf) (void)hipFree(x.d_buf);
+    if (x.h_buf) (void)hipHostFree(x.h_buf);
+  }
+  c->extra.clear();
+  return rc;
+}
+
+bool extra_inflight(hicr_ctx c) {
+  if (c->push_pending) {
+    if (hipEventQuery(c->push_ev) == hipSuccess)
+      c->push_pending = false;
+    else
+      return true;
+  }
+  for (Extra &x : c->extra)
+    if (hipEventQuery(x.ev) != hipSuccess) return true;
+  return false;
+}
+
+void destroy_extra(hicr_ctx c) {
+  wait_extra(c);
+  for (hicr_channel ch : c->channels) free_channel(ch);
+  c->channels.clear();
+  if (c->push_ev) (void)hipEventDestroy(c->push_ev);
+  c->push_ev = nullptr;
+}
+
+}  // namespace hicr
+
+extern "C" {
+
+int hicr_channel_create(hicr_ctx c, const hicr_channel_cfg *cfg, hicr_channel *out) {
+  if (!c || !cfg || !out) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  *out = nullptr;
+  const hicr_channel_cfg &k = *cfg;
+  if (k.kind != HICR_CH_FIXED && k.kind != HICR_CH_VAR) return fail(c, HICR_EINVAL, "bad kind");
+  if (k.mode > HICR_CH_MPSC_NOLOCK) return fail(c, HICR_EINVAL, "bad mode");
+  if (k.endpoints != HICR_CH_HOST && k.endpoints != HICR_CH_DEVICE)
+    return fail(c, HICR_EINVAL, "bad endpoints");
+  if (k.mode == HICR_CH_SPSC ? k.producers != 1
+                             : (k.producers < 1 || k.producers > HICR_CH_MAX_PRODUCERS))
+    return fail(c, HICR_EINVAL, "producers %u not valid for the mode", k.producers);
+  uint64_t P, E;
+  if (k.kind == HICR_CH_FIXED) {
+    if (k.token_bytes == 0 || k.capacity == 0 || k.capacity > (1ull << 40) / k.token_bytes)
+      return fail(c, HICR_EINVAL, "fixed channel needs token_bytes > 0 and capacity > 0");
+    P = k.capacity * k.token_bytes;
+    E = k.capacity;
+  } else {
+    if (k.capacity == 0 || k.entries == 0 || k.capacity > kEntrySizeMask || k.entries > (1ull << 40))
+      return fail(c, HICR_EINVAL, "variable channel needs capacity > 0 and entries > 0");
+    P = k.capacity;
+    E = k.entries;
+  }
+  const uint32_t rings = k.mode == HICR_CH_MPSC_NOLOCK ? k.producers : 1;
+  int rc = check_hbm_slot(c, k.payload, rings * P, "payload");
+  if (rc != HICR_OK) return rc;
+  rc = check_hbm_slot(c, k.entries_slot, rings * E * 8, "entries");
+  if (rc != HICR_OK) return rc;
+  if (c->slots[k.entries_slot].base % 8) return fail(c, HICR_EINVAL, "entries slot not 8-byte aligned");
+  hicr_channel ch = new (std::nothrow) hicr_channel_s();
+  if (!ch) return HICR_ENOMEM;
+  ch->ctx = c;
+  ch->cfg = k;
+  ch->n_rings = rings;
+  ch->P = P;
+  ch->E = E;
+  ch->payload_base = c->slots[k.payload].base;
+  ch->entries_base = c->slots[k.entries_slot].base;
+  const size_t bytes = sizeof(RingCoord) * rings;
+  hipError_t e;
+  if (k.endpoints == HICR_CH_HOST) {
+    void *h = nullptr;
+    e = hipHostMalloc(&h, bytes, hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) {
+      std::memset(h, 0, bytes);
+      ch->coord_host = static_cast<RingCoord *>(h);
+      void *d = nullptr;
+      e = hipHostGetDevicePointer(&d, h, 0);
+      ch->coord_dev = static_cast<RingCoord *>(d);
+    }
+    ch->rh.resize(rings);
+    for (auto &r : ch->rh) r.ent.assign(E, 0);
+  } else {
+    void *d = nullptr;
+    e = hipMalloc(&d, bytes);
+    if (e == hipSuccess) e = hipMemset(d, 0, bytes);
+    ch->coord_dev = static_cast<RingCoord *>(d);
+  }
+  if (e != hipSuccess) {
+    free_channel(ch);
+    return fail(c, HICR_ENOMEM, "coordination counters: %s", hipGetErrorString(e));
+  }
+  c->channels.push_back(ch);
+  *out = ch;
+  return HICR_OK;
+}
+
+int hicr_channel_destroy(hicr_channel ch) {
+  if (!ch) return HICR_EINVAL;
+  hicr_ctx c = ch->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!registered(c, ch)) return HICR_EINVAL;
+  (void)hipSetDevice(c->device);
+  int rc = wait_all(c);
+  c->channels.erase(std::find(c->channels.begin(), c->channels.end(), ch));
+  free_channel(ch);
+  return rc;
+}
+
+int hicr_channel_push(hicr_channel ch, uint32_t producer, hicr_slot src, uint64_t src_off,
+                      uint64_t count) {
+  if (!ch) return HICR_EINVAL;
+  hicr_ctx c = ch->ctx;
+  std::lock_guard<std::mutex> g(c->mu);  // the producers' exclusive access
+  if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
+  if (producer >= ch->cfg.producers) return fail(c, HICR_EINVAL, "no producer %u", producer);
+  const bool fixed = ch->cfg.kind == HICR_CH_FIXED;
+  uint64_t bytes, n_ent, ent_bytes;
+  if (fixed) {
+    if (count > ch->cfg.capacity) return fail(c, HICR_EINVAL, "more tokens than the ring holds");
+    bytes = count * ch->cfg.token_bytes;
+    n_ent = count;
+    ent_bytes = ch->cfg.token_bytes;
+  } else {
+    if (count > ch->P) return fail(c, HICR_EINVAL, "message larger than the ring");
+    bytes = count;
+    n_ent = 1;
+    ent_bytes = count;
+  }
+  if (src >= c->slots.size() || !c->slots[src].live) return fail(c, HICR_EBADSLOT, "bad source slot");
+  const Slot &ss = c->slots[src];
+  if (ss.space != HICR_MEM_HBM) return fail(c, HICR_EUNSUPPORTED, "source not in HBM");
+  if (src_off > ss.size || bytes > ss.size - src_off) return fail(c, HICR_ERANGE, "source range");
+  const uint32_t r = ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? producer : 0;
+  auto &h = ch->rh[r];
+  const uint64_t hm = __atomic_load_n(&ch->coord_host[r].cons.w[0], __ATOMIC_ACQUIRE);
+  const uint64_t hb = __atomic_load_n(&ch->coord_host[r].cons.w[1], __ATOMIC_ACQUIRE);
+  if ((h.tm - hm) + n_ent > ch->E || (h.tb - hb) + bytes > ch->P)
+    return HICR_EAGAIN;  // full: the consumer has not released enough room
+  if (n_ent == 0) return HICR_OK;
+  (void)hipSetDevice(c->device);
+  PushArgs pa;
+  pa.ring = dev_ring(ch, r);
+  pa.src = ss.base + src_off;
+  pa.bytes = bytes;
+  pa.pos = h.tb % ch->P;
+  pa.first_entry = h.tm;
+  pa.n_entries = (uint32_t)n_ent;
+  pa.producer = producer;
+  pa.entry_bytes = ent_bytes;
+  pa.publish = &ch->coord_dev[r].prod.w[0];
+  pa.publish_value = h.tm + n_ent;
+  hipError_t e = launch_push(pa, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(c->push_ev, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "launching a channel push");
+  c->push_pending = true;
+  for (uint64_t i = 0; i < n_ent; i++)
+    h.ent[(h.tm + i) % ch->E] = ent_bytes | ((uint64_t)producer << 48);
+  h.tm += n_ent;
+  h.tb += bytes;
+  return HICR_OK;
+}
+
+int hicr_channel_peek(hicr_channel ch, uint32_t ring, uint64_t i, uint64_t *payload_off,
+                      uint64_t *bytes, uint32_t *producer) {
+  if (!ch) return HICR_EINVAL;
+  hicr_ctx c = ch->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
+  if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
+  auto &h = ch->rh[ring];
+  const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
+  if (i >= tm - h.hm) return HICR_EAGAIN;
+  uint64_t off = h.hb;
+  for (uint64_t k = 0; k < i; k++) off += entry_size(h.ent[(h.hm + k) % ch->E]);
+  const uint64_t e = h.ent[(h.hm + i) % ch->E];
+  if (payload_off) *payload_off = ring * ch->P + off % ch->P;
+  if (bytes) *bytes = entry_size(e);
+  if (producer) *producer = (uint32_t)(e >> 48);
+  return HICR_OK;
+}
+
+int hicr_channel_pop(hicr_channel ch, uint32_t ring, uint64_t n) {
+  if (!ch) return HICR_EINVAL;
+  hicr_ctx c = ch->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
+  if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
+  auto &h = ch->rh[ring];
+  const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
+  if (n > tm - h.hm) return HICR_EAGAIN;
+  for (uint64_t k = 0; k < n; k++) h.hb += entry_size(h.ent[(h.hm + k) % ch->E]);
+  h.hm += n;
+  __atomic_store_n(&ch->coord_host[ring].cons.w[1], h.hb, __ATOMIC_RELEASE);
+  __atomic_store_n(&ch->coord_host[ring].cons.w[0], h.hm, __ATOMIC_RELEASE);
+  return HICR_OK;
+}
+
+int hicr_channel_depth(hicr_channel ch, uint32_t ring, uint64_t *msgs, uint64_t *bytes) {
+  if (!ch) return HICR_EINVAL;
+  hicr_ctx c = ch->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
+  if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
+  auto &h = ch->rh[ring];
+  const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
+  uint64_t b = 0;
+  for (uint64_t k = h.hm; k < tm; k++) b += entry_size(h.ent[k % ch->E]);
+  if (msgs) *msgs = tm - h.hm;
+  if (bytes) *bytes = b;
+  return HICR_OK;
+}
+
+int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_pump_io *io,
+                      void *stream) {
+  if (!c || !io || (n && !st)) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  if (io->n_msgs && (!io->msg_src_off || !io->msg_size))
+    return fail(c, HICR_EINVAL, "message arrays missing");
+  // channels in order of first appearance
+  std::vector<hicr_channel> chans;
+  std::map<hicr_channel, uint32_t> chan_idx;
+  std::map<std::pair<hicr_channel, uint32_t>, uint32_t> prod_stream;
+  for (uint32_t i = 0; i < n; i++) {
+    hicr_channel ch = st[i].channel;
+    if (!ch || !registered(c, ch)) return fail(c, HICR_EINVAL, "stream %u: unknown channel", i);
+    if (ch->cfg.endpoints != HICR_CH_DEVICE)
+      return fail(c, HICR_EINVAL, "stream %u: channel has host endpoints", i);
+    if (ch->broken) return fail(c, HICR_EINVAL, "stream %u: channel broken by an earlier error", i);
+    if (st[i].producer >= ch->cfg.producers) return fail(c, HICR_EINVAL, "stream %u: producer", i);
+    if (!prod_stream.emplace(std::make_pair(ch, st[i].producer), i).second)
+      return fail(c, HICR_EINVAL, "stream %u: producer already has a stream", i);
+    if (!chan_idx.count(ch)) {
+      chan_idx[ch] = (uint32_t)chans.size();
+      chans.push_back(ch);
+    }
+    if (st[i].first_msg > io->n_msgs || st[i].n_msgs > io->n_msgs - st[i].first_msg)
+      return fail(c, HICR_ERANGE, "stream %u: messages outside the arrays", i);
+    int rc = check_hbm_slot(c, st[i].src, 1, "stream source");
+    if (rc != HICR_OK) return rc;
+    rc = check_hbm_slot(c, st[i].out, 1, "stream output");
+    if (rc != HICR_OK) return rc;
+    const uint64_t src_size = c->slots[st[i].src].size;
+    uint64_t total = 0;
+    for (uint64_t j = st[i].first_msg; j < st[i].first_msg + st[i].n_msgs; j++) {
+      const uint64_t s = io->msg_size[j], o = io->msg_src_off[j];
+      if (ch->cfg.kind == HICR_CH_FIXED ? s != ch->cfg.token_bytes : s > ch->P)
+        return fail(c, HICR_EINVAL, "stream %u message %llu: size %llu", i,
+                    (unsigned long long)(j - st[i].first_msg), (unsigned long long)s);
+      if (o > src_size || s > src_size - o)
+        return fail(c, HICR_ERANGE, "stream %u message %llu outside its source", i,
+                    (unsigned long long)(j - st[i].first_msg));
+      total += s;
+    }
+    if (total > c->slots[st[i].out].size)
+      return fail(c, HICR_ERANGE, "stream %u: output slot smaller than its %llu bytes", i,
+                  (unsigned long long)total);
+  }
+  const uint32_t nch = (uint32_t)chans.size();
+  const uint32_t n_wgs = (n + 3) / 4 + nch;
+  if (n == 0) return HICR_OK;
+  if ((uint64_t)n_wgs > (uint64_t)c->n_cu * (uint64_t)c->pump_occ)
+    return fail(c, HICR_EINVAL, "%u workgroups do not fit the device at once (%d x %d)", n_wgs,
+                c->n_cu, c->pump_occ);
+  // tables
+  std::vector<DevRing> rings;
+  std::vector<DevChannel> dch(nch);
+  std::vector<uint32_t> sop;
+  uint64_t trace_total = 0;
+  for (uint32_t k = 0; k < nch; k++) {
+    hicr_channel ch = chans[k];
+    DevChannel &d = dch[k];
+    d.mode = ch->cfg.mode;
+    d.n_rings = ch->n_rings;
+    d.first_ring = (uint32_t)rings.size();
+    d.K = ch->cfg.producers;
+    d.total_msgs = 0;
+    d.prod_stream_base = (uint32_t)sop.size();
+    for (uint32_t r = 0; r < ch->n_rings; r++) rings.push_back(dev_ring(ch, r));
+    uint32_t any = 0;
+    for (uint32_t p = 0; p < d.K; p++) {
+      auto it = prod_stream.find(std::make_pair(ch, p));
+      if (it != prod_stream.end()) any = it->second;
+    }
+    for (uint32_t p = 0; p < d.K; p++) {
+      auto it = prod_stream.find(std::make_pair(ch, p));
+      sop.push_back(it != prod_stream.end() ? it->second : any);
+    }
+  }
+  std::vector<DevStream> ds(n);
+  for (uint32_t i = 0; i < n; i++) {
+    hicr_channel ch = st[i].channel;
+    const uint32_t k = chan_idx[ch];
+    ds[i].channel = k;
+    ds[i].producer = st[i].producer;
+    ds[i].ring = dch[k].first_ring + (ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? st[i].producer : 0);
+    ds[i].src_base = c->slots[st[i].src].base;
+    ds[i].out_base = c->slots[st[i].out].base;
+    ds[i].first_msg = st[i].first_msg;
+    ds[i].n_msgs = st[i].n_msgs;
+    ds[i].out_bytes = 0;
+    for (uint64_t j = st[i].first_msg; j < st[i].first_msg + st[i].n_msgs; j++)
+      ds[i].out_bytes += io->msg_size[j];
+    dch[k].total_msgs += st[i].n_msgs;
+  }
+  for (uint32_t k = 0; k < nch; k++) {
+    dch[k].trace_base = trace_total;
+    trace_total += dch[k].total_msgs;
+  }
+  if (io->trace_dev) {
+    int rc = check_dev_range(c, io->trace_dev, trace_total * 4, "trace_dev");
+    if (rc != HICR_OK) return rc;
+  }
+  if (io->ts_dev) {
+    int rc = check_dev_range(c, io->ts_dev, io->n_msgs * 16, "ts_dev");
+    if (rc != HICR_OK) return rc;
+  }
+  std::vector<DevRole> roles;
+  for (uint32_t i = 0; i < n; i += 4) {
+    DevRole r{0, std::min<uint32_t>(4, n - i), {0, 0, 0, 0}};
+    for (uint32_t w = 0; w < r.count; w++) r.ids[w] = i + w;
+    roles.push_back(r);
+  }
+  for (uint32_t k = 0; k < nch; k++) roles.push_back(DevRole{1, 1, {k, 0, 0, 0}});
+  // one upload: [err words | rings | channels | streams | sop | roles | msg_off | msg_size]
+  auto align = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+  uint64_t o_err = 0, o_ring = 256, o_ch = align(o_ring + rings.size() * sizeof(DevRing)),
+           o_st = align(o_ch + dch.size() * sizeof(DevChannel)),
+           o_sop = align(o_st + ds.size() * sizeof(DevStream)),
+           o_role = align(o_sop + sop.size() * 4), o_off = align(o_role + roles.size() * sizeof(DevRole)),
+           o_size = align(o_off + io->n_msgs * 8), total = align(o_size + io->n_msgs * 8);
+  Extra x;
+  x.pump = true;
+  hipError_t e = hipHostMalloc(&x.h_buf, total, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(c, HICR_ENOMEM, "pump staging (%llu bytes)", (unsigned long long)total);
+  e = hipMalloc(&x.d_buf, total);
+  if (e != hipSuccess) {
+    (void)hipHostFree(x.h_buf);
+    return fail(c, HICR_ENOMEM, "pump tables (%llu bytes)", (unsigned long long)total);
+  }
+  char *h = static_cast<char *>(x.h_buf);
+  std::memset(h, 0, 256);
+  std::memcpy(h + o_ring, rings.data(), rings.size() * sizeof(DevRing));
+  std::memcpy(h + o_ch, dch.data(), dch.size() * sizeof(DevChannel));
+  std::memcpy(h + o_st, ds.data(), ds.size() * sizeof(DevStream));
+  std::memcpy(h + o_sop, sop.data(), sop.size() * 4);
+  std::memcpy(h + o_role, roles.data(), roles.size() * sizeof(DevRole));
+  if (io->n_msgs) {
+    std::memcpy(h + o_off, io->msg_src_off, io->n_msgs * 8);
+    std::memcpy(h + o_size, io->msg_size, io->n_msgs * 8);
+  }
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  char *d = static_cast<char *>(x.d_buf);
+  PumpArgs a;
+  a.rings = reinterpret_cast<const DevRing *>(d + o_ring);
+  a.chans = reinterpret_cast<const DevChannel *>(d + o_ch);
+  a.streams = reinterpret_cast<const DevStream *>(d + o_st);
+  a.stream_of_prod = reinterpret_cast<const uint32_t *>(d + o_sop);
+  a.roles = reinterpret_cast<const DevRole *>(d + o_role);
+  a.msg_off = reinterpret_cast<const uint64_t *>(d + o_off);
+  a.msg_size = reinterpret_cast<const uint64_t *>(d + o_size);
+  a.trace = io->trace_dev;
+  a.ts_push = io->ts_dev;
+  a.ts_pop = io->ts_dev ? io->ts_dev + io->n_msgs : nullptr;
+  a.err = reinterpret_cast<uint32_t *>(d + o_err);
+  const uint64_t tns = io->timeout_ns ? io->timeout_ns : 10'000'000'000ull;
+  a.timeout_ticks = tns / 10;  // 100 MHz device clock
+  e = hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_pump(a, n_wgs, s);
+  // error words come back into the (no longer needed) head of the staging
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&x.ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(x.ev, s);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    if (x.ev) (void)hipEventDestroy(x.ev);
+    (void)hipFree(x.d_buf);
+    (void)hipHostFree(x.h_buf);
+    return hip_fail(c, e, "launching the channel pump");
+  }
+  x.abort_word = a.err + 1;
+  x.chans = chans;
+  {
+    std::lock_guard<std::mutex> ga(c->abort_mu);
+    c->abort_words.push_back(x.abort_word);
+  }
+  c->extra.push_back(x);
+  return HICR_OK;
+}
+
+int hicr_channel_abort(hicr_ctx c) {
+  if (!c) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->abort_mu);  // not c->mu: a fence may hold it
+  (void)hipSetDevice(c->device);
+  static const uint32_t one = 1;
+  for (uint32_t *w : c->abort_words) {
+    hipError_t e = hipMemcpyAsync(w, &one, 4, hipMemcpyHostToDevice, c->abort_stream);
+    if (e != hipSuccess) return fail(nullptr, HICR_EDEVICE, "abort");
+  }
+  return hipStreamSynchronize(c->abort_stream) == hipSuccess ? HICR_OK : HICR_EDEVICE;
+}
+
+}  // extern "C"

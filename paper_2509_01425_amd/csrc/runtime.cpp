@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "hicr.h"
+#include "chan.h"
 #include "internal.h"
 #include "runtime.h"
 
@@ -272,6 +273,9 @@ int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
   ok = ok && hipMalloc(&c->d_words, kNumSubs * 64) == hipSuccess;
   ok = ok && hipMemset(c->d_words, 0, kNumSubs * 64) == hipSuccess;
   ok = ok && hipHostMalloc(&c->h_read, 64, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->push_ev, hipEventDisableTiming) == hipSuccess;
+  if (ok && (pump_occupancy(&c->pump_occ) != 0 || c->pump_occ < 1)) c->pump_occ = 1;
   for (int i = 0; ok && i < kNumSubs; i++) {
     ok = hipEventCreateWithFlags(&c->subs[i].ev, hipEventDisableTiming) == hipSuccess;
     c->subs[i].grid_done = reinterpret_cast<uint32_t *>(c->d_words + 64 * i);
@@ -290,6 +294,7 @@ int hicr_ctx_destroy(hicr_ctx c) {
   (void)hipSetDevice(c->device);
   wait_all(c);
   destroy_extra(c);
+  destroy_sched(c);
   for (Sub &s : c->subs) {
     if (s.h) (void)hipHostFree(s.h);
     if (s.d) (void)hipFree(s.d);
@@ -299,6 +304,7 @@ int hicr_ctx_destroy(hicr_ctx c) {
   if (c->d_words) (void)hipFree(c->d_words);
   if (c->h_read) (void)hipHostFree(c->h_read);
   if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->abort_stream) (void)hipStreamDestroy(c->abort_stream);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return HICR_OK;

@@ -10,6 +10,8 @@
 #include "hicr.h"
 #include "internal.h"
 
+struct hicr_channel_s;
+
 namespace hicr {
 
 struct Slot {
@@ -34,6 +36,17 @@ constexpr int kNumSubs = 4;
 
 struct SchedState;  // autotuned table and device-resident network (sched.cpp)
 
+// Asynchronous work other than copy submissions (channel pushes, pumps):
+// its event, and buffers to free once it has completed.
+struct Extra {
+  hipEvent_t ev = nullptr;
+  void *d_buf = nullptr;
+  void *h_buf = nullptr;
+  bool pump = false;
+  uint32_t *abort_word = nullptr;
+  std::vector<struct ::hicr_channel_s *> chans;
+};
+
 }  // namespace hicr
 
 struct hicr_ctx_s {
@@ -54,6 +67,14 @@ struct hicr_ctx_s {
   std::vector<hicr_desc> pending;
   hicr_sched def_sched{};
   hicr::SchedState *sched = nullptr;
+  std::vector<struct hicr_channel_s *> channels;
+  std::vector<hicr::Extra> extra;
+  int pump_occ = 0;  // pump workgroups per CU
+  hipEvent_t push_ev = nullptr;  // last host-API channel push
+  bool push_pending = false;
+  std::mutex abort_mu;  // guards abort_words; never held while waiting on the GPU
+  std::vector<uint32_t *> abort_words;
+  hipStream_t abort_stream = nullptr;
   std::string err;
 };
 
@@ -70,9 +91,12 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
 int flush_pending(hicr_ctx c);
 int ensure_counter_capacity(hicr_ctx c, uint32_t nslots);
 
-// Hooks implemented by the schedule selector (sched.cpp).
+// Schedule selection (sched.cpp).
 int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out,
                  const DevSched **sched_dev, hipStream_t stream);
+void destroy_sched(hicr_ctx c);
+
+// Channel pushes and pumps (channel.cpp).
 int wait_extra(hicr_ctx c);
 bool extra_inflight(hicr_ctx c);
 void destroy_extra(hicr_ctx c);

@@ -10,9 +10,7 @@ int choose_sched(hicr_ctx c, const hicr_desc *, uint64_t, uint32_t mode, hicr_sc
   return fail(c, HICR_EINVAL, "schedule mode %u is not available on this context", mode);
 }
 
-int wait_extra(hicr_ctx) { return HICR_OK; }
-bool extra_inflight(hicr_ctx) { return false; }
-void destroy_extra(hicr_ctx c) {
+void destroy_sched(hicr_ctx c) {
   delete c->sched;
   c->sched = nullptr;
 }

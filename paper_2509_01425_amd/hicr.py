@@ -48,6 +48,32 @@ class hicr_sched(ctypes.Structure):
                 ("unroll", ctypes.c_uint32), ("mode", ctypes.c_uint32)]
 
 
+CH_FIXED, CH_VAR = 0, 1
+CH_SPSC, CH_MPSC_LOCK, CH_MPSC_NOLOCK = 0, 1, 2
+CH_HOST, CH_DEVICE = 0, 1
+CH_MAX_PRODUCERS = 64
+
+
+class hicr_channel_cfg(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("producers", ctypes.c_uint32), ("endpoints", ctypes.c_uint32),
+                ("token_bytes", ctypes.c_uint64), ("capacity", ctypes.c_uint64),
+                ("entries", ctypes.c_uint64), ("payload", ctypes.c_uint32),
+                ("entries_slot", ctypes.c_uint32)]
+
+
+class hicr_stream(ctypes.Structure):
+    _fields_ = [("channel", ctypes.c_void_p), ("producer", ctypes.c_uint32),
+                ("src", ctypes.c_uint32), ("out", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("first_msg", ctypes.c_uint64), ("n_msgs", ctypes.c_uint64)]
+
+
+class hicr_pump_io(ctypes.Structure):
+    _fields_ = [("msg_src_off", ctypes.c_void_p), ("msg_size", ctypes.c_void_p),
+                ("n_msgs", ctypes.c_uint64), ("trace_dev", ctypes.c_void_p),
+                ("ts_dev", ctypes.c_void_p), ("timeout_ns", ctypes.c_uint64)]
+
+
 _u32, _u64, _vp, _int = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
 _pu32, _pu64, _pvp = ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_vp)
 
@@ -65,6 +91,15 @@ _SIGNATURES = {
     "hicr_memcpy_batch": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_sched), _vp, _pu64]),
     "hicr_fence": (_int, [_vp]),
     "hicr_fence_slot": (_int, [_vp, _u32, _u64, _u64, _u64]),
+    "hicr_channel_create": (_int, [_vp, ctypes.POINTER(hicr_channel_cfg), _pvp]),
+    "hicr_channel_destroy": (_int, [_vp]),
+    "hicr_channel_push": (_int, [_vp, _u32, _u32, _u64, _u64]),
+    "hicr_channel_peek": (_int, [_vp, _u32, _u64, _pu64, _pu64, _pu32]),
+    "hicr_channel_pop": (_int, [_vp, _u32, _u64]),
+    "hicr_channel_depth": (_int, [_vp, _u32, _pu64, _pu64]),
+    "hicr_channel_pump": (_int, [_vp, ctypes.POINTER(hicr_stream), _u32,
+                                 ctypes.POINTER(hicr_pump_io), _vp]),
+    "hicr_channel_abort": (_int, [_vp]),
 }
 
 _lib = None
@@ -159,3 +194,59 @@ def hicr_fence(ctx) -> int:
 
 def hicr_fence_slot(ctx, slot: int, exp_sent: int, exp_recv: int, timeout_ns: int) -> int:
     return lib().hicr_fence_slot(ctx, slot, exp_sent, exp_recv, timeout_ns)
+
+
+# --------------------------------------------------------------- channels
+
+def make_channel_cfg(kind, mode, producers, endpoints, payload, entries_slot,
+                     token_bytes=0, capacity=0, entries=0):
+    return hicr_channel_cfg(kind, mode, producers, endpoints, token_bytes, capacity, entries,
+                            payload, entries_slot)
+
+
+def hicr_channel_create(ctx, cfg: hicr_channel_cfg):
+    out = _vp()
+    rc = lib().hicr_channel_create(ctx, ctypes.byref(cfg), ctypes.byref(out))
+    return rc, out.value
+
+
+def hicr_channel_destroy(ch) -> int:
+    return lib().hicr_channel_destroy(ch)
+
+
+def hicr_channel_push(ch, producer: int, src: int, src_off: int, count: int) -> int:
+    return lib().hicr_channel_push(ch, producer, src, src_off, count)
+
+
+def hicr_channel_peek(ch, ring: int, i: int):
+    off, size, prod = _u64(), _u64(), _u32()
+    rc = lib().hicr_channel_peek(ch, ring, i, ctypes.byref(off), ctypes.byref(size),
+                                 ctypes.byref(prod))
+    return rc, off.value, size.value, prod.value
+
+
+def hicr_channel_pop(ch, ring: int, n: int) -> int:
+    return lib().hicr_channel_pop(ch, ring, n)
+
+
+def hicr_channel_depth(ch, ring: int):
+    m, b = _u64(), _u64()
+    rc = lib().hicr_channel_depth(ch, ring, ctypes.byref(m), ctypes.byref(b))
+    return rc, m.value, b.value
+
+
+def hicr_channel_pump(ctx, streams, msg_src_off: np.ndarray, msg_size: np.ndarray,
+                      trace_dev: int = 0, ts_dev: int = 0, timeout_ns: int = 0, stream: int = 0):
+    """streams: sequence of (channel, producer, src_slot, out_slot, first_msg, n_msgs)."""
+    arr = (hicr_stream * max(len(streams), 1))()
+    for i, (ch, p, src, out, first, n) in enumerate(streams):
+        arr[i] = hicr_stream(ch, p, src, out, 0, first, n)
+    off = np.ascontiguousarray(msg_src_off, dtype=np.uint64)
+    size = np.ascontiguousarray(msg_size, dtype=np.uint64)
+    io = hicr_pump_io(off.ctypes.data if off.size else None, size.ctypes.data if size.size else None,
+                      off.size, trace_dev or None, ts_dev or None, timeout_ns)
+    return lib().hicr_channel_pump(ctx, arr, len(streams), ctypes.byref(io), stream or None)
+
+
+def hicr_channel_abort(ctx) -> int:
+    return lib().hicr_channel_abort(ctx)

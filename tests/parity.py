@@ -53,3 +53,53 @@ def oracle_counters(descs, n_slots):
         _, s, r = c.counters(k)
         out[k] = (s, r)
     return out
+
+
+def oracle_fifo_outputs(P, E, stream_msgs):
+    """Consumer output of one SPSC (or non-locking MPSC sub-) ring: the
+    oracle's variable ring driven by a sequential schedule (push while there
+    is room, otherwise read and pop the oldest), so the output is the order
+    the oracle's FIFO defines.  stream_msgs: list of uint8 arrays."""
+    ch = oracle.VChan(P, E)
+    out = []
+    for m in stream_msgs:
+        while True:
+            rc = ch.push(m, len(m))
+            if rc == oracle.OK:
+                break
+            assert rc == oracle.EAGAIN
+            rc, data, _ = ch.read(0)
+            out.append(data)
+            assert ch.pop(1) == oracle.OK
+    while ch.depth()[0]:
+        rc, data, _ = ch.read(0)
+        out.append(data)
+        assert ch.pop(1) == oracle.OK
+    return np.concatenate(out) if out else np.zeros(0, np.uint8)
+
+
+def oracle_locking_outputs(P, E, K, order, stream_msgs_by_prod):
+    """Outputs of a locking MPSC channel whose consumer took producers'
+    messages in ``order`` (list of producer ids): the oracle's shared tagged
+    ring replays that merge; the consumer routes by the entry's producer."""
+    ch = oracle.MPSC(K, P, E, locking=True)
+    nxt = [0] * K
+    outs = [[] for _ in range(K)]
+    ring = ch.ring_for(0)
+    for p in order:
+        m = stream_msgs_by_prod[p][nxt[p]]
+        nxt[p] += 1
+        while True:
+            rc = ch.push(p, m, len(m))
+            if rc == oracle.OK:
+                break
+            assert rc == oracle.EAGAIN
+            rc, data, prod = ring.read(0)
+            outs[prod].append(data)
+            assert ring.pop(1) == oracle.OK
+    while ring.depth()[0]:
+        rc, data, prod = ring.read(0)
+        outs[prod].append(data)
+        assert ring.pop(1) == oracle.OK
+    assert nxt == [len(x) for x in stream_msgs_by_prod], "trace is not a merge of the streams"
+    return [np.concatenate(o) if o else np.zeros(0, np.uint8) for o in outs]

@@ -1,0 +1,359 @@
+"""GPU parity of the ring channels against the CPU oracle.
+
+Host-API channels run in lock step with the oracle's rings (identical return
+codes, offsets, sizes, producers and bytes).  Device pumps are checked per
+stream against the outputs the oracle's rings produce for the same messages;
+locking MPSC channels are checked by replaying the device's consumption
+order through the oracle's shared ring (which also proves the order is a
+merge of the producers' FIFO sequences).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import oracle_fifo_outputs, oracle_locking_outputs
+from workloads import channels as wc
+from workloads.content import content
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2509_01425_amd import hicr as H
+    from workloads import device as wd
+    rc, ctx = H.hicr_ctx_create(0, 0)
+    assert rc == H.OK
+    yield torch, H, wd, ctx
+    assert H.hicr_ctx_destroy(ctx) == H.OK
+
+
+def _reg(H, ctx, t, off=0, size=None):
+    size = t.numel() * t.element_size() - off if size is None else size
+    rc, s = H.hicr_slot_register(ctx, t.data_ptr() + off, size, H.MEM_HBM)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    return s
+
+
+def test_host_fixed_spsc_lockstep(env):
+    """The tiny channel: 16 tokens x 256 B, 1,000 tokens, seeded attempts."""
+    torch, H, wd, ctx = env
+    C, T, N, seed = 16, 256, 1000, 31
+    _say("host fixed spsc")
+    src = torch.empty(N * T, dtype=torch.uint8, device="cuda")
+    wd.fill(src.data_ptr(), N * T, seed)
+    ring = torch.zeros(C * T, dtype=torch.uint8, device="cuda")
+    ent = torch.zeros(C, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    ss, rs, es = _reg(H, ctx, src), _reg(H, ctx, ring), _reg(H, ctx, ent)
+    cfg = H.make_channel_cfg(H.CH_FIXED, H.CH_SPSC, 1, H.CH_HOST, rs, es, token_bytes=T, capacity=C)
+    rc, ch = H.hicr_channel_create(ctx, cfg)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    oc = oracle.FChan(C, T)
+    host_src = content(seed, 0, N * T)
+    sent = popped = 0
+    n_eagain = 0
+    for kind, k in wc.tiny_schedule() + [("pop", 1)] * (2 * N):
+        if popped == N:
+            break
+        if kind == "push":
+            k = min(k, N - sent)
+            if k == 0:
+                continue
+            rc = H.hicr_channel_push(ch, 0, ss, sent * T, k)
+            assert rc == oc.push(host_src[sent * T:], k)
+            n_eagain += rc == H.EAGAIN
+            if rc == H.OK:
+                sent += k
+                assert H.hicr_fence(ctx) == H.OK
+        else:
+            depth = oc.depth()
+            assert H.hicr_channel_depth(ch, 0) == (H.OK, depth, depth * T)
+            if depth:
+                dev_ring = ring.cpu().numpy()
+            for i in range(min(k, depth)):
+                rc, off, sz, prod = H.hicr_channel_peek(ch, 0, i)
+                ro, ooff = oc.peek(i)
+                assert (rc, off, sz, prod) == (ro, ooff, T, 0)
+                assert np.array_equal(dev_ring[off:off + T], oc.ring[ooff:ooff + T])
+            if k > depth:
+                assert H.hicr_channel_peek(ch, 0, depth)[0] == H.EAGAIN
+            rc = H.hicr_channel_pop(ch, 0, k)
+            assert rc == oc.pop(k)
+            popped += k if rc == H.OK else 0
+    assert popped == N and sent == N and n_eagain > 10
+    # rejections
+    assert H.hicr_channel_push(ch, 0, ss, 0, C + 1) == H.EINVAL
+    assert H.hicr_channel_push(ch, 1, ss, 0, 1) == H.EINVAL
+    assert H.hicr_channel_push(ch, 0, ss, N * T - T + 1, 1) == H.ERANGE
+    assert H.hicr_channel_push(ch, 0, 99999, 0, 1) == H.EBADSLOT
+    assert H.hicr_channel_destroy(ch) == H.OK
+
+
+@pytest.mark.parametrize("P,E", [(4096 + 13, 8), (257, 3)])
+def test_host_variable_spsc_lockstep(env, P, E):
+    torch, H, wd, ctx = env
+    seed = 57
+    _say("host var spsc", P, E)
+    g = np.random.default_rng(P)
+    src_n = 1 << 16
+    src = torch.empty(src_n, dtype=torch.uint8, device="cuda")
+    wd.fill(src.data_ptr(), src_n, seed)
+    ring = torch.zeros(P, dtype=torch.uint8, device="cuda")
+    ent = torch.zeros(E, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    ss, rs, es = _reg(H, ctx, src), _reg(H, ctx, ring), _reg(H, ctx, ent)
+    rc, ch = H.hicr_channel_create(ctx, H.make_channel_cfg(H.CH_VAR, H.CH_SPSC, 1, H.CH_HOST, rs, es,
+                                                           capacity=P, entries=E))
+    assert rc == H.OK
+    oc = oracle.VChan(P, E)
+    host_src = content(seed, 0, src_n)
+    for step in range(600):
+        if g.random() < 0.55:
+            s = int(g.choice([0, 1, 15, 16, 17, P // 3, P // 2, P - 1, P, P + 1, int(g.integers(0, P))]))
+            off = int(g.integers(0, src_n - s))
+            rc = H.hicr_channel_push(ch, 0, ss, off, s)
+            assert rc == oc.push(host_src[off:off + s], s)
+            if rc == H.OK:
+                assert H.hicr_fence(ctx) == H.OK
+        else:
+            n = int(g.integers(0, 3))
+            m, b = oc.depth()
+            assert H.hicr_channel_depth(ch, 0) == (H.OK, m, b)
+            if m:
+                dev_ring = ring.cpu().numpy()
+                for i in range(min(n, m)):
+                    rc, off, sz, _ = H.hicr_channel_peek(ch, 0, i)
+                    ro, ooff, osz, _ = oc.peek(i)
+                    assert (rc, off, sz) == (ro, ooff, osz)
+                    got = np.concatenate([dev_ring[off:], dev_ring[:off]])[:sz]  # follows the wrap
+                    assert np.array_equal(got, oc.read(i)[1])
+            assert H.hicr_channel_pop(ch, 0, n) == oc.pop(n)
+    assert H.hicr_channel_destroy(ch) == H.OK
+
+
+@pytest.mark.parametrize("mode", ["lock", "nolock"])
+def test_host_mpsc_lockstep(env, mode):
+    torch, H, wd, ctx = env
+    K, P, E, seed = 3, 2000, 4, 77
+    _say("host mpsc", mode)
+    g = np.random.default_rng(5)
+    rings = 1 if mode == "lock" else K
+    src_n = 1 << 15
+    src = torch.empty(src_n, dtype=torch.uint8, device="cuda")
+    wd.fill(src.data_ptr(), src_n, seed)
+    ring = torch.zeros(rings * P, dtype=torch.uint8, device="cuda")
+    ent = torch.zeros(rings * E, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    ss, rs, es = _reg(H, ctx, src), _reg(H, ctx, ring), _reg(H, ctx, ent)
+    hmode = H.CH_MPSC_LOCK if mode == "lock" else H.CH_MPSC_NOLOCK
+    rc, ch = H.hicr_channel_create(ctx, H.make_channel_cfg(H.CH_VAR, hmode, K, H.CH_HOST, rs, es,
+                                                           capacity=P, entries=E))
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    oc = oracle.MPSC(K, P, E, locking=(mode == "lock"))
+    host_src = content(seed, 0, src_n)
+    for step in range(500):
+        if g.random() < 0.55:
+            p = int(g.integers(0, K))
+            s = int(g.integers(0, 900))
+            off = int(g.integers(0, src_n - s))
+            rc = H.hicr_channel_push(ch, p, ss, off, s)
+            assert rc == oc.push(p, host_src[off:off + s], s)
+            if rc == H.OK:
+                assert H.hicr_fence(ctx) == H.OK
+        else:
+            r = int(g.integers(0, rings))
+            oring = oc.rings[r]
+            m, b = oring.depth()
+            assert H.hicr_channel_depth(ch, r) == (H.OK, m, b)
+            if m:
+                dev = ring.cpu().numpy()[r * P:(r + 1) * P]
+                rc, off, sz, prod = H.hicr_channel_peek(ch, r, 0)
+                ro, ooff, osz, oprod = oring.peek(0)
+                assert (rc, off - r * P, sz) == (ro, ooff, osz)
+                assert prod == (oprod if mode == "lock" else r)
+                local = off - r * P
+                got = np.concatenate([dev[local:], dev[:local]])[:sz]
+                assert np.array_equal(got, oring.read(0)[1])
+            assert H.hicr_channel_pop(ch, r, 1) == oring.pop(1)
+    assert H.hicr_channel_push(ch, K, ss, 0, 1) == H.EINVAL
+    assert H.hicr_channel_destroy(ch) == H.OK
+
+
+def test_channel_create_rejections(env):
+    torch, H, wd, ctx = env
+    buf = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    b = _reg(H, ctx, buf)
+    small = _reg(H, ctx, buf, 0, 100)
+    cfg = H.make_channel_cfg
+    assert H.hicr_channel_create(ctx, cfg(H.CH_VAR, H.CH_SPSC, 2, H.CH_HOST, b, b, capacity=64,
+                                          entries=4))[0] == H.EINVAL
+    assert H.hicr_channel_create(ctx, cfg(H.CH_VAR, H.CH_MPSC_LOCK, 65, H.CH_HOST, b, b,
+                                          capacity=64, entries=4))[0] == H.EINVAL
+    assert H.hicr_channel_create(ctx, cfg(H.CH_VAR, H.CH_SPSC, 1, H.CH_HOST, small, b,
+                                          capacity=101, entries=4))[0] == H.ERANGE
+    assert H.hicr_channel_create(ctx, cfg(H.CH_FIXED, H.CH_SPSC, 1, H.CH_HOST, b, b,
+                                          token_bytes=0, capacity=4))[0] == H.EINVAL
+    assert H.hicr_channel_create(ctx, cfg(H.CH_VAR, H.CH_MPSC_NOLOCK, 4, H.CH_HOST, b, small,
+                                          capacity=16, entries=4))[0] == H.ERANGE
+    rc, dch = H.hicr_channel_create(ctx, cfg(H.CH_VAR, H.CH_SPSC, 1, H.CH_DEVICE, b, b,
+                                             capacity=64, entries=4))
+    assert rc == H.OK
+    assert H.hicr_channel_push(dch, 0, b, 0, 1) == H.EINVAL     # device endpoints
+    assert H.hicr_channel_destroy(dch) == H.OK
+
+
+def test_pump_tiny_fixed_spsc(env):
+    """The tiny channel driven by a producer wave and a consumer workgroup."""
+    torch, H, wd, ctx = env
+    C, T, N, seed = 16, 256, 1000, 91
+    _say("pump tiny fixed")
+    src = torch.empty(N * T, dtype=torch.uint8, device="cuda")
+    wd.fill(src.data_ptr(), N * T, seed)
+    out = torch.zeros(N * T, dtype=torch.uint8, device="cuda")
+    ring = torch.zeros(C * T, dtype=torch.uint8, device="cuda")
+    ent = torch.zeros(C, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    ss, os_, rs, es = _reg(H, ctx, src), _reg(H, ctx, out), _reg(H, ctx, ring), _reg(H, ctx, ent)
+    rc, ch = H.hicr_channel_create(ctx, H.make_channel_cfg(H.CH_FIXED, H.CH_SPSC, 1, H.CH_DEVICE,
+                                                           rs, es, token_bytes=T, capacity=C))
+    assert rc == H.OK
+    offs = np.arange(N, dtype=np.uint64) * T
+    sizes = np.full(N, T, dtype=np.uint64)
+    for rep in range(2):   # the channel is reusable: counters continue
+        out.zero_()
+        torch.cuda.synchronize()
+        assert H.hicr_channel_pump(ctx, [(ch, 0, ss, os_, 0, N)], offs, sizes) == H.OK
+        assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+        host_src = content(seed, 0, N * T)
+        want = oracle_fifo_outputs(C * T, C, [host_src[i * T:(i + 1) * T] for i in range(N)])
+        assert np.array_equal(out.cpu().numpy(), want)
+    bad = sizes.copy()
+    bad[5] = T - 1
+    assert H.hicr_channel_pump(ctx, [(ch, 0, ss, os_, 0, N)], offs, bad) == H.EINVAL
+    assert H.hicr_channel_destroy(ch) == H.OK
+
+
+def _check_plan(torch, H, rig, plan, seed, mode, trace, sample=None):
+    """Compare the pump's outputs with the oracle for every (or sampled) stream."""
+    out = rig["out"]
+    tr = trace.cpu().numpy() if trace is not None else None
+    # trace bases per channel (channels appear in stream order)
+    per_chan = np.bincount(plan.stream_channel, weights=np.diff(plan.msg_begin),
+                           minlength=plan.n_channels).astype(np.int64)
+    base = np.concatenate([[0], np.cumsum(per_chan)[:-1]])
+    msgs = {}
+
+    def stream_msgs(s):
+        if s not in msgs:
+            b0, b1 = int(plan.msg_begin[s]), int(plan.msg_begin[s + 1])
+            src0 = s * plan.src_bytes
+            blob = content(seed, src0, plan.src_bytes)
+            msgs[s] = [blob[int(o):int(o) + int(z)] for o, z in
+                       zip(plan.msg_src_off[b0:b1], plan.msg_size[b0:b1])]
+        return msgs[s]
+
+    streams = range(plan.n_streams) if sample is None else sample
+    checked = set()
+    for s in streams:
+        c = int(plan.stream_channel[s])
+        if c < plan.n_spsc or mode == "nolock":
+            want = oracle_fifo_outputs(plan.P, plan.E, stream_msgs(s))
+            got_streams = [(s, want)]
+        else:
+            if c in checked:
+                continue
+            checked.add(c)
+            sids = [x for x in range(plan.n_streams) if plan.stream_channel[x] == c]
+            order_sid = tr[base[c]:base[c] + per_chan[c]]
+            prod_of = {sid: int(plan.stream_producer[sid]) for sid in sids}
+            order = [prod_of[int(x)] for x in order_sid]
+            by_prod = [None] * plan.K
+            for sid in sids:
+                by_prod[prod_of[sid]] = stream_msgs(sid)
+            outs = oracle_locking_outputs(plan.P, plan.E, plan.K, order, by_prod)
+            got_streams = [(sid, outs[prod_of[sid]]) for sid in sids]
+        for sid, want in got_streams:
+            o = int(rig["out_off"][sid])
+            got = out[o:o + len(want)].cpu().numpy()
+            assert np.array_equal(got, want), ("stream", sid)
+    if tr is not None:
+        # every channel's consumption order holds each of its streams n_msgs times
+        for c in range(plan.n_channels):
+            seg = tr[base[c]:base[c] + per_chan[c]]
+            sids = [x for x in range(plan.n_streams) if plan.stream_channel[x] == c]
+            cnt = np.bincount(seg, minlength=plan.n_streams)
+            for sid in sids:
+                assert cnt[sid] == plan.msg_begin[sid + 1] - plan.msg_begin[sid]
+
+
+@pytest.mark.parametrize("mode", ["lock", "nolock"])
+def test_pump_small_mixed_plan(env, mode):
+    """6 SPSC + 3 MPSC x 3 producers, small rings (8 KiB, 8 entries) so that
+    producers wait for room and messages wrap; message sizes up to the ring."""
+    torch, H, wd, ctx = env
+    from bench import channel_rig
+    seed = 404
+    _say("pump small", mode)
+    plan = wc.plan(n_spsc=6, n_mpsc=3, K=3, total_msgs=1500, lo=1, hi=8192, P=8192, E=8,
+                   src_bytes=1 << 16, batch=7)
+    hmode = H.CH_MPSC_LOCK if mode == "lock" else H.CH_MPSC_NOLOCK
+    rig = channel_rig(torch, H, ctx, plan, hmode, seed)
+    trace = torch.zeros(plan.n_msgs, dtype=torch.int32, device="cuda")
+    ts = torch.zeros(2 * plan.n_msgs, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    rc = H.hicr_channel_pump(ctx, rig["streams"], plan.msg_src_off, plan.msg_size,
+                             trace.data_ptr(), ts.data_ptr(), timeout_ns=5 * 10**9)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+    _check_plan(torch, H, rig, plan, seed, mode, trace)
+    t = ts.cpu().numpy().reshape(2, -1)
+    assert (t[1] >= t[0]).all() and (t[0] > 0).all()
+    for ch in rig["channels"]:
+        assert H.hicr_channel_destroy(ch) == H.OK
+
+
+@pytest.mark.parametrize("mode", ["lock", "nolock"])
+def test_pump_full_size_sampled(env, mode):
+    """The measured channel configuration: 1,024 SPSC + 64 MPSC x 8 producers,
+    1e6 messages of 16 B..256 KiB through 1 MiB / 64-entry rings, in one
+    persistent launch.  Sampled streams are checked byte for byte (every
+    stream of the sampled MPSC channels), every channel's consumption order is
+    checked to hold each of its streams' messages."""
+    torch, H, wd, ctx = env
+    from bench import channel_rig
+    seed = 808
+    _say("pump full", mode)
+    plan = wc.plan()
+    hmode = H.CH_MPSC_LOCK if mode == "lock" else H.CH_MPSC_NOLOCK
+    rig = channel_rig(torch, H, ctx, plan, hmode, seed)
+    trace = torch.zeros(plan.n_msgs, dtype=torch.int32, device="cuda")
+    ts = torch.zeros(2 * plan.n_msgs, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    rc = H.hicr_channel_pump(ctx, rig["streams"], plan.msg_src_off, plan.msg_size,
+                             trace.data_ptr(), ts.data_ptr(), timeout_ns=10 * 10**9)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    payload = int(plan.msg_size.sum())
+    t = ts.cpu().numpy().reshape(2, -1).astype(np.int64)
+    lat_us = (t[1] - t[0]) / 100.0
+    _say(f"pump {mode}: {ms:.2f} ms, {4 * payload / ms / 1e6:.0f} GB/s (4 x payload), "
+         f"latency p50 {np.percentile(lat_us, 50):.1f} us p99 {np.percentile(lat_us, 99):.1f} us")
+    g = np.random.default_rng(1)
+    sample = list(g.choice(plan.n_spsc, 6, replace=False)) + \
+        [s for s in range(plan.n_streams) if plan.stream_channel[s] in (plan.n_spsc, plan.n_spsc + 37)]
+    _check_plan(torch, H, rig, plan, seed, mode, trace, sample=sample)
+    for ch in rig["channels"]:
+        assert H.hicr_channel_destroy(ch) == H.OK
+    del rig
+    torch.cuda.empty_cache()

@@ -292,3 +292,20 @@ def test_channel_plan_shape():
     assert (p.msg_src_off + p.msg_size <= p.src_bytes).all()
     assert 25e9 < int(p.msg_size.sum()) < 29e9           # ~27.0 GB of payload
     assert (np.bincount(p.stream_channel) == np.r_[np.ones(1024), 8 * np.ones(64)]).all()
+
+
+@pytest.mark.parametrize("P,E,msgs", [(4, 2, [[2, 1], [1, 2]]), (5, 3, [[2, 1], [1, 2], [3]]),
+                                      (3, 1, [[1, 1], [2]])])
+def test_protocol_reservation_locking_accepts(P, E, msgs):
+    """Locking MPSC that holds the lock only for the room check and the
+    reservation, copies outside it and publishes in lock order."""
+    assert protocol.explore(P, E, msgs, locking=True, reserve=True) > 50
+
+
+def test_protocol_reservation_catches_unordered_publish_and_no_lock():
+    with pytest.raises(protocol.Violation):
+        protocol.explore(4, 3, [[2, 1], [1, 2]], locking=True, reserve=True,
+                         variant=protocol.Variant(unordered_publish=True))
+    with pytest.raises(protocol.Violation):
+        protocol.explore(4, 2, [[2, 1], [1, 2]], locking=True, reserve=True,
+                         variant=protocol.Variant(no_lock=True))
