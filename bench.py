@@ -138,6 +138,233 @@ def channel_rig(torch, H, ctx, plan, mpsc_mode, seed, stream=0):
             "payload": payload, "entries": entries, "channels": chans}
 
 
+def bench_channels(torch, H, mpsc_mode, steps=3, warmup=1, seed=5):
+    """The channel configuration (1,024 SPSC + 64 MPSC x 8 producers, 1e6
+    messages, 1 MiB / 64-entry rings) through one persistent pump per step.
+    GB/s counts 4 bytes per payload byte (source read, ring write, ring read,
+    output write) plus the 8-byte entry written and read per message."""
+    from workloads import channels as wc
+    plan = wc.plan()
+    stream = torch.cuda.Stream()
+    rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
+    assert rc == H.OK
+    rig = channel_rig(torch, H, ctx, plan, mpsc_mode, seed, stream.cuda_stream)
+    ts = torch.zeros(2 * plan.n_msgs, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    times = []
+    for k in range(warmup + steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rc = H.hicr_channel_pump(ctx, rig["streams"], plan.msg_src_off, plan.msg_size, 0,
+                                 ts.data_ptr(), timeout_ns=10 * 10**9)
+        e1.record(stream)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+        if k >= warmup:
+            times.append(e0.elapsed_time(e1))
+    t = ts.cpu().numpy().reshape(2, -1).astype(np.int64)
+    lat_us = (t[1] - t[0]) / 100.0
+    payload = int(plan.msg_size.sum())
+    moved = 4 * payload + 16 * plan.n_msgs
+    ms = float(np.mean(times))
+    for ch in rig["channels"]:
+        H.hicr_channel_destroy(ch)
+    H.hicr_ctx_destroy(ctx)
+    del rig
+    torch.cuda.empty_cache()
+    return {"mpsc_mode": "locking" if mpsc_mode == H.CH_MPSC_LOCK else "non-locking",
+            "value": round(moved / ms / 1e6, 1), "unit": "GB/s", "ms_per_pump": round(ms, 3),
+            "frac_of_peak": round(moved / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "messages": plan.n_msgs, "payload_bytes": payload,
+            "latency_p50_us": round(float(np.percentile(lat_us, 50)), 2),
+            "latency_p99_us": round(float(np.percentile(lat_us, 99)), 2)}
+
+
+def bench_learned(torch, H, n_train=20000, n_test=1000, reps=3, epochs=30, batch=256, lr=1e-3,
+                  save=None):
+    """The learned-schedule configuration.  Every batch of the training law
+    (tiny-like or batched-like family, 8..4096 requests) is autotuned over the
+    12 classes (median of `reps` timed runs); the network is trained on the
+    GPU by the library's kernels on the first n_train batches (Adam, 30
+    epochs of 256) and judged on the n_test held-out batches by measured
+    copy time against the best fixed class of the training set, the untuned
+    default class, the tuned table (nearest training batch) and the
+    autotuner's per-batch best."""
+    from workloads import memcpy as wm
+    from workloads.mlp_init import he_uniform
+    t_start = time.time()
+    stream = torch.cuda.Stream()
+    rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
+    assert rc == H.OK
+    from workloads import device as wd
+    pool = torch.empty(wm.B_POOL, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), wm.B_POOL, 3, 0, stream.cuda_stream)
+    bases, sizes = wm.batched_slots()
+    slots = np.empty(len(bases), dtype=np.uint32)
+    for k, (b, sz) in enumerate(zip(bases, sizes)):
+        rc, slots[k] = H.hicr_slot_register(ctx, pool.data_ptr() + int(b), int(sz), H.MEM_HBM)
+    torch.cuda.synchronize()
+    N = n_train + n_test
+    X = np.zeros((N, 32), np.float32)
+    T = np.zeros((N, 12), np.float32)
+    nbytes = np.zeros(N, np.float64)
+
+    def batch_descs(b):
+        d, _ = wm.family(b)
+        d["dst_slot"] = slots[d["dst_slot"]]
+        d["src_slot"] = slots[d["src_slot"]]
+        return d
+
+    for b in range(N):
+        d = batch_descs(b)
+        rc, times, _ = H.hicr_autotune(ctx, d, reps)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        X[b] = H.hicr_sched_features(d)[1]
+        T[b] = times
+        nbytes[b] = 2.0 * float(d["size"].sum())
+        if b % 2000 == 0:
+            print(f"autotune {b}/{N} ({time.time() - t_start:.0f} s)", file=sys.stderr, flush=True)
+    y = np.argmin(T, axis=1).astype(np.int32)
+    tr, te = slice(0, n_train), slice(n_train, N)
+    # training on the GPU; the shuffles are seeded inputs
+    assert H.hicr_mlp_set_params(ctx, he_uniform(0)) == H.OK
+    xd = torch.from_numpy(X[tr]).cuda()
+    yd = torch.from_numpy(y[tr]).cuda()
+    g = np.random.default_rng(np.random.SeedSequence([0x48694352, 3, 99]))
+    t0 = time.time()
+    for ep in range(epochs):
+        perm = torch.from_numpy(g.permutation(n_train)).cuda()
+        for i in range(0, n_train - batch + 1, batch):
+            idx = perm[i:i + batch]
+            xb, yb = xd[idx].contiguous(), yd[idx].contiguous()
+            assert H.hicr_mlp_train_step(ctx, xb.data_ptr(), yb.data_ptr(), batch, lr) == H.OK
+    assert H.hicr_fence(ctx) == H.OK
+    train_s = time.time() - t0
+    logits = torch.zeros(n_test, 12, dtype=torch.float32, device="cuda")
+    xt = torch.from_numpy(X[te]).cuda()
+    assert H.hicr_mlp_forward(ctx, xt.data_ptr(), n_test, logits.data_ptr()) == H.OK
+    pred = np.argmax(logits.cpu().numpy(), axis=1)
+    fixed = int(np.argmin(T[tr].sum(axis=0)))
+    default = 4
+    # tuned table: nearest training feature (the same rule the library applies)
+    for b in range(n_train):
+        H.hicr_tune_add(ctx, batch_descs(b), int(y[b]))
+    Xtr = X[tr]
+    nn_cls = np.array([y[int(np.argmin(((Xtr - X[n_train + i]) ** 2).sum(1)))] for i in range(n_test)])
+    Tt = T[te]
+    rows = np.arange(n_test)
+
+    def by_labels(choice):
+        t = float(Tt[rows, choice].sum())
+        return {"gbps": round(float(nbytes[te].sum()) / t / 1e6, 1),
+                "regret": round(t / float(Tt.min(axis=1).sum()) - 1.0, 4)}
+
+    table = {"autotuner_best": by_labels(np.argmin(Tt, axis=1)),
+             "fixed_best": by_labels(np.full(n_test, fixed)),
+             "default": by_labels(np.full(n_test, default)),
+             "tuned_table": by_labels(nn_cls),
+             "learned": by_labels(pred)}
+    # measured end to end through the submission path (median of 3 per batch)
+    def measured(sched):
+        tot = 0.0
+        for i in range(n_test):
+            d = batch_descs(n_train + i)
+            ms = []
+            for _ in range(3):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rc, _ = H.hicr_memcpy_batch(ctx, d, sched)
+                e1.record(stream)
+                assert rc == H.OK
+                assert H.hicr_fence(ctx) == H.OK
+                ms.append(e0.elapsed_time(e1))
+            tot += float(np.median(ms))
+        return {"gbps": round(float(nbytes[te].sum()) / tot / 1e6, 1), "total_ms": round(tot, 2)}
+
+    meas = {"fixed_best": measured(H.hicr_sched_class(fixed)[1]),
+            "default": measured(H.hicr_sched_class(default)[1]),
+            "tuned_table": measured(H.make_sched(65536, 1, 2, H.SCHED_TUNED)),
+            "learned": measured(H.make_sched(65536, 1, 2, H.SCHED_LEARNED))}
+    out = {"workload": "learned schedule: family batches (8..4096 requests, tiny-like or "
+                       "batched-like sizes), 12 classes, median of %d" % reps,
+           "n_train": n_train, "n_test": n_test, "fixed_best_class": fixed,
+           "label_hist": np.bincount(y, minlength=12).tolist(),
+           "accuracy": round(float((pred == y[te]).mean()), 4),
+           "tuned_accuracy": round(float((nn_cls == y[te]).mean()), 4),
+           "train_seconds": round(train_s, 2), "by_autotune_times": table,
+           "measured": meas, "wall_seconds": round(time.time() - t_start, 1)}
+    if save:
+        rc, params = H.hicr_mlp_get_params(ctx)
+        np.savez(save, X=X, T=T, nbytes=nbytes, params=params)
+    H.hicr_ctx_destroy(ctx)
+    del pool
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(torch, H, duration_s=60.0, rate=2000.0, budget=200_000_000_000, streams=4,
+                  max_batch=64, batch=0):
+    """The serving configuration: Poisson arrivals (2,000 requests/s), each a
+    memcpy batch (8..512 requests, 64 B..16 MiB) or a burst (1..256 messages,
+    16 B..256 KiB) through one of 1,024 SPSC channels; admission by an HBM
+    arena budget; continuous batching over `streams` launches in flight."""
+    from workloads import device as wd
+    from workloads import serving as ws
+    src_bytes, P, E, nch = 16 << 30, 1 << 20, 64, 1024
+    t_gen = time.time()
+    tr = ws.trace(duration_s=duration_s, rate=rate, src_bytes=src_bytes, n_channels=nch,
+                  batch=batch)
+    t_gen = time.time() - t_gen
+    stream = torch.cuda.Stream()
+    rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
+    assert rc == H.OK
+    src = torch.empty(src_bytes, dtype=torch.uint8, device="cuda")
+    wd.fill(src.data_ptr(), src_bytes, 77, 0, stream.cuda_stream)
+    arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    payload = torch.empty(nch * P, dtype=torch.uint8, device="cuda")
+    entries = torch.zeros(nch * E, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    _, ss = H.hicr_slot_register(ctx, src.data_ptr(), src_bytes)
+    _, aslot = H.hicr_slot_register(ctx, arena.data_ptr(), budget)
+    chans = []
+    for c in range(nch):
+        _, ps = H.hicr_slot_register(ctx, payload.data_ptr() + c * P, P)
+        _, es = H.hicr_slot_register(ctx, entries.data_ptr() + c * E * 8, E * 8)
+        rc, ch = H.hicr_channel_create(ctx, H.make_channel_cfg(H.CH_VAR, H.CH_SPSC, 1, H.CH_DEVICE,
+                                                               ps, es, capacity=P, entries=E))
+        assert rc == H.OK
+        chans.append(ch)
+    n = len(tr.reqs)
+    admit = np.zeros(n, np.uint64)
+    fin = np.zeros(n, np.uint64)
+    rc, st = H.hicr_serve(ctx, tr.reqs, aslot, ss, tr.descs, tr.msg_src_off, tr.msg_size, chans,
+                          streams=streams, max_batch_reqs=max_batch, admit_ns=admit, done_ns=fin)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    arr = tr.reqs["arrival_ns"].astype(np.int64)
+    lat_ms = (fin.astype(np.int64) - arr) / 1e6
+    wait_ms = (admit.astype(np.int64) - arr) / 1e6
+    kinds = tr.reqs["kind"]
+    out = {"requests": n, "duration_s": duration_s, "rate": rate, "budget_bytes": budget,
+           "value": round(tr.algorithmic_bytes() / (st.wall_ns / 1e9) / 1e9, 1), "unit": "GB/s",
+           "latency_p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+           "latency_p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+           "copy_latency_p99_ms": round(float(np.percentile(lat_ms[kinds == 0], 99)), 3),
+           "burst_latency_p99_ms": round(float(np.percentile(lat_ms[kinds == 1], 99)), 3),
+           "queue_wait_p50_ms": round(float(np.percentile(wait_ms, 50)), 3),
+           "queue_wait_p99_ms": round(float(np.percentile(wait_ms, 99)), 3),
+           "peak_arena_bytes": int(st.peak_arena_bytes), "copy_launches": int(st.copy_launches),
+           "pump_launches": int(st.pump_launches),
+           "max_inflight_requests": int(st.max_inflight_requests),
+           "wall_s": round(st.wall_ns / 1e9, 3), "trace_gen_s": round(t_gen, 1)}
+    for ch in chans:
+        H.hicr_channel_destroy(ch)
+    H.hicr_ctx_destroy(ctx)
+    del arena, src, payload, entries
+    torch.cuda.empty_cache()
+    return out
+
+
 def parse_sched(H, text):
     if text in ("tuned", "learned"):
         return H.make_sched(64 << 10, 1, 2, H.SCHED_TUNED if text == "tuned" else H.SCHED_LEARNED)
@@ -154,6 +381,14 @@ def main():
     ap.add_argument("--sched", default="4")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-channels", action="store_true")
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "channels", "learned", "serving"])
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-budget", type=float, default=200e9)
+    ap.add_argument("--learned-train", type=int, default=20000)
+    ap.add_argument("--learned-test", type=int, default=1000)
+    ap.add_argument("--learned-save", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -167,6 +402,21 @@ def main():
     from paper_2509_01425_amd import hicr as H
     from workloads import device as wd
     from workloads import memcpy as wm
+
+    if args.workload == "learned":
+        res = bench_learned(torch, H, n_train=args.learned_train, n_test=args.learned_test,
+                            save=args.learned_save)
+        print(json.dumps({"learned": res}), flush=True)
+        return
+    if args.workload == "serving":
+        res = bench_serving(torch, H, duration_s=args.serve_seconds, budget=int(args.serve_budget))
+        print(json.dumps({"serving": res}), flush=True)
+        return
+    if args.workload == "channels":
+        res = [bench_channels(torch, H, m, steps=args.steps, warmup=args.warmup)
+               for m in (H.CH_MPSC_LOCK, H.CH_MPSC_NOLOCK)]
+        print(json.dumps({"channels": res}), flush=True)
+        return
 
     stream = torch.cuda.Stream()
     rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
@@ -237,6 +487,8 @@ def main():
     H.hicr_ctx_destroy(ctx)
     del pool
     torch.cuda.empty_cache()
+    if not args.no_channels:
+        out["channels"] = [bench_channels(torch, H, m) for m in (H.CH_MPSC_LOCK, H.CH_MPSC_NOLOCK)]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wm.batched(0))
     print(json.dumps(out), flush=True)

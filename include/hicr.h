@@ -151,6 +151,49 @@ int hicr_fence_slot(hicr_ctx ctx, hicr_slot slot, uint64_t exp_sent, uint64_t ex
                     uint64_t timeout_ns);
 
 
+
+/* ------------------------------------------- schedule selection (growth) */
+/* The batch feature used to pick a schedule: bin b of 32 counts the requests
+ * with floor(log2 size) == b (bins above 31 fold into 31, size 0 into bin 0);
+ * out32[b] = log2(1 + count).  Host-only; needs no context. */
+int hicr_sched_features(const hicr_desc *descs, uint64_t n, float *out32);
+
+/* Autotuner: run the batch under each of the 12 classes, `reps` timed runs
+ * (1..64) after one warm-up, and store the median copy-kernel time of each
+ * class in times_ms[12] (and the fastest class, ties to the lowest, in
+ * *best_or_null).  The bytes really move (13 * reps times in all), so the
+ * batch must be hazard-free; slot counters are not raised.  Synchronous. */
+int hicr_autotune(hicr_ctx ctx, const hicr_desc *descs, uint64_t n, uint32_t reps,
+                  float *times_ms, uint32_t *best_or_null);
+/* Tuned table used by HICR_SCHED_TUNED: each entry is an autotuned batch's
+ * feature and its best class; a batch takes the class of the nearest entry
+ * (squared distance of features).  With an empty table the context default
+ * schedule is used. */
+int hicr_tune_add(hicr_ctx ctx, const hicr_desc *descs, uint64_t n, uint32_t cls);
+int hicr_tune_clear(hicr_ctx ctx);
+
+/* The schedule network, 32 -> 64 -> 64 -> 12 with ReLU, fp32, parameters in
+ * the flat layout W1[64][32] b1[64] W2[64][64] b2[64] W3[12][64] b3[12]
+ * (7,052 floats).  Loading parameters enables HICR_SCHED_LEARNED, in which a
+ * device kernel computes the batch feature from the uploaded sizes, runs the
+ * network and hands the argmax class (ties to the lowest) to the copy kernel
+ * without a host round trip.  Without a network HICR_SCHED_LEARNED falls back
+ * to the tuned table.  x_dev: [batch][32] features, y_dev: [batch] class
+ * labels, logits_dev: [batch][12], grad_dev: [7052] (all device memory). */
+int hicr_mlp_set_params(hicr_ctx ctx, const float *params); /* also resets Adam */
+int hicr_mlp_get_params(hicr_ctx ctx, float *params_out);
+int hicr_mlp_forward(hicr_ctx ctx, const float *x_dev, uint32_t batch, float *logits_dev);
+/* Class the network chose for the most recent HICR_SCHED_LEARNED submission
+ * (waits for that submission to complete). */
+int hicr_last_choice(hicr_ctx ctx, uint32_t *cls);
+/* Gradient of the mean softmax cross-entropy (and the mean loss, if loss_dev). */
+int hicr_mlp_grad(hicr_ctx ctx, const float *x_dev, const int32_t *y_dev, uint32_t batch,
+                  float *grad_dev, float *loss_dev);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on one mini-batch; asynchronous
+ * on the context stream, completed by hicr_fence. */
+int hicr_mlp_train_step(hicr_ctx ctx, const float *x_dev, const int32_t *y_dev, uint32_t batch,
+                        float lr, float *loss_dev);
+
 /* -------------------------------------------------------------- channels */
 /* Sec. 4.3 Channels: circular buffers pre-allocated at the consumer.  The
  * caller registers the payload ring(s) and the entry ring(s) as HBM slots;
@@ -256,6 +299,73 @@ int hicr_channel_pump(hicr_ctx ctx, const hicr_stream *streams, uint32_t n_strea
                       const hicr_pump_io *io, void *stream);
 /* Ask running pumps of this context to stop (they end at their next wait). */
 int hicr_channel_abort(hicr_ctx ctx);
+
+/* ------------------------------------------------------ serving (growth) */
+/* A continuous-batching server on one context.  Requests arrive over time
+ * (arrival_ns from the start of the run, non-decreasing); each is a memcpy
+ * batch or a channel burst and needs hbm_bytes of the arena (an HBM slot that
+ * is the serving budget) for its destinations.  In arrival order, a request
+ * is admitted as soon as its destinations fit in the arena; every request
+ * admitted since the last launch is fused into one copy launch (memcpy
+ * batches, with the given schedule) and one pump launch (bursts; at most one
+ * burst per channel per launch); up to `streams` launches are in flight so
+ * new work overlaps work already running.  When a launch completes, each of
+ * its requests is timestamped and passed to on_complete while its results
+ * are still in the arena; then its arena space is freed.  on_complete runs on
+ * the calling thread and must not call into the library on this context.
+ *
+ *   HICR_REQ_COPY:  descs[first .. first+count): dst_off relative to the
+ *                   request's arena block, src_off in slot `src`; slot ids in
+ *                   the descriptors are ignored.  hbm_bytes >= every
+ *                   dst_off + size.
+ *   HICR_REQ_BURST: messages first .. first+count of msg_src_off/msg_size, read
+ *                   from slot `src` and pushed through channels[channel] (a
+ *                   device-endpoint channel, producer 0); the consumer writes
+ *                   them back to back at the start of the request's block.
+ * Synchronous: returns when every request has completed (or on the first
+ * error, after draining the launches in flight). */
+#define HICR_REQ_COPY 0u
+#define HICR_REQ_BURST 1u
+typedef struct {
+  uint32_t kind;
+  uint32_t channel;
+  uint64_t first;
+  uint64_t count;
+  uint64_t hbm_bytes;
+  uint64_t arrival_ns;
+} hicr_request;
+
+typedef struct {
+  hicr_slot arena;
+  hicr_slot src;
+  uint32_t streams;        /* launches in flight, 1..4 */
+  uint32_t max_batch_reqs; /* requests fused into one launch, >= 1 */
+  const hicr_desc *descs;
+  uint64_t n_descs;
+  const uint64_t *msg_src_off;
+  const uint64_t *msg_size;
+  uint64_t n_msgs;
+  const hicr_channel *channels;
+  uint32_t n_channels;
+  uint32_t pad;
+  const hicr_sched *sched_or_null; /* copy schedule; TUNED / LEARNED allowed */
+  void (*on_complete)(void *user, uint64_t request, uint64_t arena_off);
+  void *user;
+  uint64_t *admit_ns;  /* optional [n]: when each request was admitted    */
+  uint64_t *done_ns;   /* optional [n]: when its completion was observed  */
+} hicr_serve_cfg;
+
+typedef struct {
+  uint64_t completed;
+  uint64_t peak_arena_bytes;
+  uint64_t copy_launches;
+  uint64_t pump_launches;
+  uint64_t max_inflight_requests;
+  uint64_t wall_ns;
+} hicr_serve_stats;
+
+int hicr_serve(hicr_ctx ctx, const hicr_request *requests, uint64_t n, const hicr_serve_cfg *cfg,
+               hicr_serve_stats *stats_or_null);
 
 #ifdef __cplusplus
 }

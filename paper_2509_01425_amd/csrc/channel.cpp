@@ -102,24 +102,9 @@ int wait_extra(hicr_ctx c) {
   }
   for (Extra &x : c->extra) {
     hipError_t e = hipEventSynchronize(x.ev);
-    if (e != hipSuccess) {
-      rc = hip_fail(c, e, "waiting for a pump");
-    } else if (x.pump) {
-      const uint32_t *err = static_cast<const uint32_t *>(x.h_buf);
-      if (err[0] & kErrCorrupt) rc = fail(c, HICR_EDEVICE, "a channel pump read a malformed entry");
-      else if (err[0] & kErrTimeout) rc = fail(c, HICR_ETIMEDOUT, "a channel pump made no progress");
-      else if (err[1]) rc = fail(c, HICR_EDEVICE, "a channel pump was aborted");
-      if (err[0] || err[1])
-        for (hicr_channel ch : x.chans) ch->broken = true;
-    }
-    {
-      std::lock_guard<std::mutex> g(c->abort_mu);
-      c->abort_words.erase(std::remove(c->abort_words.begin(), c->abort_words.end(), x.abort_word),
-                           c->abort_words.end());
-    }
-    (void)hipEventDestroy(x.ev);
-    if (x.d_buf) (void)hipFree(x.d_buf);
-    if (x.h_buf) (void)hipHostFree(x.h_buf);
+    if (e != hipSuccess) rc = hip_fail(c, e, "waiting for a pump");
+    int r = pump_finish(c, x);
+    if (rc == HICR_OK) rc = r;
   }
   c->extra.clear();
   return rc;
@@ -334,13 +319,18 @@ int hicr_channel_depth(hicr_channel ch, uint32_t ring, uint64_t *msgs, uint64_t 
   return HICR_OK;
 }
 
-int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_pump_io *io,
-                      void *stream) {
-  if (!c || !io || (n && !st)) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  if (io->n_msgs && (!io->msg_src_off || !io->msg_size))
-    return fail(c, HICR_EINVAL, "message arrays missing");
+}  // extern "C"
+
+namespace hicr {
+
+// Validate a pump plan whose streams carry resolved addresses, build the
+// device tables and launch.  The caller holds c->mu.  On success the launch
+// is described by *x (event, buffers to free, abort word, channels).
+int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *msg_off,
+                const uint64_t *msg_size, uint64_t n_msgs, uint32_t *trace_dev, uint64_t *ts_dev,
+                uint64_t timeout_ns, hipStream_t s, Extra *xout) {
+  const uint32_t n = (uint32_t)st.size();
+  if (n_msgs && (!msg_off || !msg_size)) return fail(c, HICR_EINVAL, "message arrays missing");
   // channels in order of first appearance
   std::vector<hicr_channel> chans;
   std::map<hicr_channel, uint32_t> chan_idx;
@@ -358,26 +348,21 @@ int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_
       chan_idx[ch] = (uint32_t)chans.size();
       chans.push_back(ch);
     }
-    if (st[i].first_msg > io->n_msgs || st[i].n_msgs > io->n_msgs - st[i].first_msg)
+    if (st[i].first_msg > n_msgs || st[i].n_msgs > n_msgs - st[i].first_msg)
       return fail(c, HICR_ERANGE, "stream %u: messages outside the arrays", i);
-    int rc = check_hbm_slot(c, st[i].src, 1, "stream source");
-    if (rc != HICR_OK) return rc;
-    rc = check_hbm_slot(c, st[i].out, 1, "stream output");
-    if (rc != HICR_OK) return rc;
-    const uint64_t src_size = c->slots[st[i].src].size;
     uint64_t total = 0;
     for (uint64_t j = st[i].first_msg; j < st[i].first_msg + st[i].n_msgs; j++) {
-      const uint64_t s = io->msg_size[j], o = io->msg_src_off[j];
-      if (ch->cfg.kind == HICR_CH_FIXED ? s != ch->cfg.token_bytes : s > ch->P)
+      const uint64_t sz = msg_size[j], o = msg_off[j];
+      if (ch->cfg.kind == HICR_CH_FIXED ? sz != ch->cfg.token_bytes : sz > ch->P)
         return fail(c, HICR_EINVAL, "stream %u message %llu: size %llu", i,
-                    (unsigned long long)(j - st[i].first_msg), (unsigned long long)s);
-      if (o > src_size || s > src_size - o)
+                    (unsigned long long)(j - st[i].first_msg), (unsigned long long)sz);
+      if (o > st[i].src_size || sz > st[i].src_size - o)
         return fail(c, HICR_ERANGE, "stream %u message %llu outside its source", i,
                     (unsigned long long)(j - st[i].first_msg));
-      total += s;
+      total += sz;
     }
-    if (total > c->slots[st[i].out].size)
-      return fail(c, HICR_ERANGE, "stream %u: output slot smaller than its %llu bytes", i,
+    if (total > st[i].out_size)
+      return fail(c, HICR_ERANGE, "stream %u: output smaller than its %llu bytes", i,
                   (unsigned long long)total);
   }
   const uint32_t nch = (uint32_t)chans.size();
@@ -418,25 +403,25 @@ int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_
     ds[i].channel = k;
     ds[i].producer = st[i].producer;
     ds[i].ring = dch[k].first_ring + (ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? st[i].producer : 0);
-    ds[i].src_base = c->slots[st[i].src].base;
-    ds[i].out_base = c->slots[st[i].out].base;
+    ds[i].src_base = st[i].src_base;
+    ds[i].out_base = st[i].out_base;
     ds[i].first_msg = st[i].first_msg;
     ds[i].n_msgs = st[i].n_msgs;
     ds[i].out_bytes = 0;
     for (uint64_t j = st[i].first_msg; j < st[i].first_msg + st[i].n_msgs; j++)
-      ds[i].out_bytes += io->msg_size[j];
+      ds[i].out_bytes += msg_size[j];
     dch[k].total_msgs += st[i].n_msgs;
   }
   for (uint32_t k = 0; k < nch; k++) {
     dch[k].trace_base = trace_total;
     trace_total += dch[k].total_msgs;
   }
-  if (io->trace_dev) {
-    int rc = check_dev_range(c, io->trace_dev, trace_total * 4, "trace_dev");
+  if (trace_dev) {
+    int rc = check_dev_range(c, trace_dev, trace_total * 4, "trace_dev");
     if (rc != HICR_OK) return rc;
   }
-  if (io->ts_dev) {
-    int rc = check_dev_range(c, io->ts_dev, io->n_msgs * 16, "ts_dev");
+  if (ts_dev) {
+    int rc = check_dev_range(c, ts_dev, n_msgs * 16, "ts_dev");
     if (rc != HICR_OK) return rc;
   }
   std::vector<DevRole> roles;
@@ -452,7 +437,7 @@ int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_
            o_st = align(o_ch + dch.size() * sizeof(DevChannel)),
            o_sop = align(o_st + ds.size() * sizeof(DevStream)),
            o_role = align(o_sop + sop.size() * 4), o_off = align(o_role + roles.size() * sizeof(DevRole)),
-           o_size = align(o_off + io->n_msgs * 8), total = align(o_size + io->n_msgs * 8);
+           o_size = align(o_off + n_msgs * 8), total = align(o_size + n_msgs * 8);
   Extra x;
   x.pump = true;
   hipError_t e = hipHostMalloc(&x.h_buf, total, hipHostMallocDefault);
@@ -469,11 +454,10 @@ int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_
   std::memcpy(h + o_st, ds.data(), ds.size() * sizeof(DevStream));
   std::memcpy(h + o_sop, sop.data(), sop.size() * 4);
   std::memcpy(h + o_role, roles.data(), roles.size() * sizeof(DevRole));
-  if (io->n_msgs) {
-    std::memcpy(h + o_off, io->msg_src_off, io->n_msgs * 8);
-    std::memcpy(h + o_size, io->msg_size, io->n_msgs * 8);
+  if (n_msgs) {
+    std::memcpy(h + o_off, msg_off, n_msgs * 8);
+    std::memcpy(h + o_size, msg_size, n_msgs * 8);
   }
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   char *d = static_cast<char *>(x.d_buf);
   PumpArgs a;
   a.rings = reinterpret_cast<const DevRing *>(d + o_ring);
@@ -483,11 +467,11 @@ int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_
   a.roles = reinterpret_cast<const DevRole *>(d + o_role);
   a.msg_off = reinterpret_cast<const uint64_t *>(d + o_off);
   a.msg_size = reinterpret_cast<const uint64_t *>(d + o_size);
-  a.trace = io->trace_dev;
-  a.ts_push = io->ts_dev;
-  a.ts_pop = io->ts_dev ? io->ts_dev + io->n_msgs : nullptr;
+  a.trace = trace_dev;
+  a.ts_push = ts_dev;
+  a.ts_pop = ts_dev ? ts_dev + n_msgs : nullptr;
   a.err = reinterpret_cast<uint32_t *>(d + o_err);
-  const uint64_t tns = io->timeout_ns ? io->timeout_ns : 10'000'000'000ull;
+  const uint64_t tns = timeout_ns ? timeout_ns : 10'000'000'000ull;
   a.timeout_ticks = tns / 10;  // 100 MHz device clock
   e = hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_pump(a, n_wgs, s);
@@ -508,8 +492,66 @@ int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_
     std::lock_guard<std::mutex> ga(c->abort_mu);
     c->abort_words.push_back(x.abort_word);
   }
-  c->extra.push_back(x);
+  *xout = x;
   return HICR_OK;
+}
+
+// Outcome of a finished pump (its event has completed): release its buffers
+// and report a device-side error.
+int pump_finish(hicr_ctx c, Extra &x) {
+  int rc = HICR_OK;
+  const uint32_t *err = static_cast<const uint32_t *>(x.h_buf);
+  if (err[0] & kErrCorrupt) rc = fail(c, HICR_EDEVICE, "a channel pump read a malformed entry");
+  else if (err[0] & kErrTimeout) rc = fail(c, HICR_ETIMEDOUT, "a channel pump made no progress");
+  else if (err[1]) rc = fail(c, HICR_EDEVICE, "a channel pump was aborted");
+  if (err[0] || err[1])
+    for (hicr_channel ch : x.chans) ch->broken = true;
+  {
+    std::lock_guard<std::mutex> g(c->abort_mu);
+    c->abort_words.erase(std::remove(c->abort_words.begin(), c->abort_words.end(), x.abort_word),
+                         c->abort_words.end());
+  }
+  (void)hipEventDestroy(x.ev);
+  if (x.d_buf) (void)hipFree(x.d_buf);
+  if (x.h_buf) (void)hipHostFree(x.h_buf);
+  x = Extra();
+  return rc;
+}
+
+uint64_t channel_payload_limit(hicr_channel ch) {
+  return ch->cfg.kind == HICR_CH_FIXED ? ch->cfg.token_bytes : ch->P;
+}
+
+}  // namespace hicr
+
+extern "C" {
+
+int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_pump_io *io,
+                      void *stream) {
+  if (!c || !io || (n && !st)) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  std::vector<PumpStream> ps(n);
+  for (uint32_t i = 0; i < n; i++) {
+    int rc = check_hbm_slot(c, st[i].src, 1, "stream source");
+    if (rc != HICR_OK) return rc;
+    rc = check_hbm_slot(c, st[i].out, 1, "stream output");
+    if (rc != HICR_OK) return rc;
+    ps[i].channel = st[i].channel;
+    ps[i].producer = st[i].producer;
+    ps[i].src_base = c->slots[st[i].src].base;
+    ps[i].src_size = c->slots[st[i].src].size;
+    ps[i].out_base = c->slots[st[i].out].base;
+    ps[i].out_size = c->slots[st[i].out].size;
+    ps[i].first_msg = st[i].first_msg;
+    ps[i].n_msgs = st[i].n_msgs;
+  }
+  Extra x;
+  int rc = pump_launch(c, ps, io->msg_src_off, io->msg_size, io->n_msgs, io->trace_dev,
+                       io->ts_dev, io->timeout_ns,
+                       stream ? static_cast<hipStream_t>(stream) : c->stream, &x);
+  if (rc == HICR_OK && x.ev) c->extra.push_back(x);
+  return rc;
 }
 
 int hicr_channel_abort(hicr_ctx c) {

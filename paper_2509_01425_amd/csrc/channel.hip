@@ -15,10 +15,14 @@
 // consumer polls them round robin.
 //
 // pump_kernel is persistent: every workgroup is either four independent
-// producer waves (one stream each) or one consumer (all four waves).  The
-// host launches no more workgroups than the device holds at once, and every
-// wait gives up after a no-progress time-out or on the abort word, so every
-// wave exits.
+// producer waves (one stream each) or one consumer (all four waves).  Waits
+// poll with relaxed device-scope loads and take one acquire fence once the
+// condition holds (an acquire per poll would invalidate the L2 on every
+// spin).  Producers publish up to 8 messages per release; consumers take up
+// to 16 per release across all of a channel's rings, and copy each batch as
+// one index space of 16-byte vectors.  The host launches no more workgroups
+// than the device holds at once, and every wait gives up after a
+// no-progress time-out or on the abort word, so every wave exits.
 #include "chan.h"
 
 namespace hicr {
@@ -27,7 +31,6 @@ namespace hicr {
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef v4u v4u_any __attribute__((aligned(1)));
 
-constexpr uint32_t kBatch = 8;  // messages a consumer takes per notification
 
 __device__ __forceinline__ uint64_t ld_acq(uint64_t a) {
   return __hip_atomic_load((uint64_t *)a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -83,14 +86,6 @@ __device__ __forceinline__ void ring_put(const DevRing &r, uint64_t pos, uint64_
   if (n > first) team_copy<TEAM, U>(r.payload, src + first, n - first, t);
 }
 
-template <int TEAM, int U>
-__device__ __forceinline__ void ring_get(const DevRing &r, uint64_t pos, uint64_t dst, uint64_t n,
-                                         uint32_t t) {
-  uint64_t first = r.P - pos < n ? r.P - pos : n;
-  team_copy<TEAM, U>(dst, r.payload + pos, first, t);
-  if (n > first) team_copy<TEAM, U>(dst + first, r.payload, n - first, t);
-}
-
 // No-progress watchdog for spin waits.
 struct Watch {
   uint64_t deadline, span;
@@ -109,12 +104,97 @@ struct Watch {
   }
 };
 
-__device__ __forceinline__ uint64_t wave_bcast(uint64_t v) {
-  return ((uint64_t)__shfl((unsigned)(v >> 32), 0) << 32) | (uint64_t)__shfl((unsigned)v, 0);
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  return ((uint64_t)__shfl((unsigned)(v >> 32), src) << 32) | (uint64_t)__shfl((unsigned)v, src);
 }
 
-// One producer wave drives one stream.
-__device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane) {
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_scan(uint64_t v, uint32_t lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t t = ((uint64_t)__shfl_up((unsigned)(v >> 32), o) << 32) | __shfl_up((unsigned)v, o);
+    if (lane >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A contiguous piece of a batched copy: n bytes d <- s.  a0 is the first
+// 16-byte-aligned destination byte inside it (clipped), nv its 16-byte body
+// vectors, v0 the body vectors of all earlier segments.
+struct Seg {
+  uint64_t d, s, n, a0, nv, v0;
+};
+
+__device__ __forceinline__ Seg make_seg(uint64_t d, uint64_t s, uint64_t n) {
+  Seg g;
+  g.d = d;
+  g.s = s;
+  g.n = n;
+  uint64_t a0 = (d + 15) & ~(uint64_t)15;
+  if (a0 > d + n) a0 = d + n;
+  uint64_t a1 = (d + n) & ~(uint64_t)15;
+  if (a1 < a0) a1 = a0;
+  g.a0 = a0;
+  g.nv = (a1 - a0) >> 4;
+  g.v0 = 0;
+  return g;
+}
+
+// All TEAM threads copy nseg segments (held in LDS) as one index space of
+// 16-byte vectors, so a batch of small messages costs about one memory round
+// trip instead of one per message.  Head and tail bytes go one by one.
+template <int TEAM, int U>
+__device__ void seg_copy(const Seg *sg, uint32_t nseg, uint64_t total_v, uint32_t t) {
+  for (uint32_t x = t; x < nseg * 32; x += TEAM) {
+    const Seg &g = sg[x >> 5];
+    const uint32_t j = x & 31;
+    const uint64_t a1 = g.a0 + 16 * g.nv;
+    if (j < 16) {
+      if (j < g.a0 - g.d)
+        *(GLOBAL unsigned char *)(g.d + j) = *(const GLOBAL unsigned char *)(g.s + j);
+    } else if (j - 16 < g.d + g.n - a1) {
+      const uint64_t o = (a1 - g.d) + (j - 16);
+      *(GLOBAL unsigned char *)(g.d + o) = *(const GLOBAL unsigned char *)(g.s + o);
+    }
+  }
+  for (uint64_t b = 0; b < total_v; b += (uint64_t)TEAM * U) {
+    v4u r[U];
+    uint64_t da[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      const uint64_t v = b + t + (uint64_t)k * TEAM;
+      da[k] = 0;
+      if (v < total_v) {
+        uint32_t lo = 0, hi = nseg;  // last segment with v0 <= v
+        while (hi - lo > 1) {
+          uint32_t mid = (lo + hi) >> 1;
+          if (sg[mid].v0 <= v) lo = mid; else hi = mid;
+        }
+        const Seg &g = sg[lo];
+        const uint64_t w = v - g.v0;
+        r[k] = *(const GLOBAL v4u_any *)(g.s + (g.a0 - g.d) + 16 * w);
+        da[k] = g.a0 + 16 * w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; k++)
+      if (da[k]) *(GLOBAL v4u *)(da[k]) = r[k];
+  }
+}
+
+constexpr uint32_t kProdBatch = 8;   // messages a producer publishes at once
+constexpr uint32_t kConsBatch = 16;  // messages a consumer takes at once
+
+// One producer wave drives one stream: it takes as many of its next messages
+// as the ring has room for (up to kProdBatch), copies them as one batch,
+// writes their entries and publishes them with one release.
+__device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane, Seg *sg) {
   const DevStream st = a.streams[sid];
   const DevRing r = a.rings[st.ring];
   const bool locking = a.chans[st.channel].mode == kModeMpscLock;
@@ -127,71 +207,126 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane) {
   uint64_t tm = ld_acq(tm_a), tb = ld_acq(hb_a);
   Watch w{0, a.timeout_ticks, a.err};
   w.progress();
-  for (uint64_t m = 0; m < st.n_msgs; m++) {
-    const uint64_t s = a.msg_size[st.first_msg + m];
-    const uint64_t off = a.msg_off[st.first_msg + m];
-    uint64_t my_tm = tm, my_tb = tb;
+  uint64_t m = 0;
+  while (m < st.n_msgs) {
+    // sizes and offsets of the next kProdBatch messages, one per lane
+    const bool have = lane < kProdBatch && m + lane < st.n_msgs;
+    const uint64_t sz = have ? a.msg_size[st.first_msg + m + lane] : 0;
+    const uint64_t off = have ? a.msg_off[st.first_msg + m + lane] : 0;
+    const uint64_t incl = wave_scan(sz, lane);
+    uint64_t ticket = 0;
     if (locking) {
-      uint64_t ticket = 0;
       if (lane == 0)
         ticket = __hip_atomic_fetch_add((uint64_t *)tk_a, 1ull, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
-      ticket = wave_bcast(ticket);
-      while (ld_acq(sv_a) != ticket) {
+      ticket = shfl64(ticket, 0);
+      while (ld_rlx(sv_a) != ticket) {
         __builtin_amdgcn_s_sleep(1);
         if (w.expired()) return;
       }
-      my_tm = ld_rlx(rm_a);
-      my_tb = ld_rlx(rb_a);
-      while (!(my_tm - ld_acq(hm_a) < r.E && my_tb - ld_acq(hb_a) + s <= r.P)) {
-        __builtin_amdgcn_s_sleep(2);
-        if (w.expired()) return;
-      }
-      if (lane == 0) {
-        st_rlx(rm_a, my_tm + 1);
-        st_rlx(rb_a, my_tb + s);
-        st_rel(sv_a, ticket + 1);
-      }
-    } else {
-      while (!(my_tm - ld_acq(hm_a) < r.E && my_tb - ld_acq(hb_a) + s <= r.P)) {
-        __builtin_amdgcn_s_sleep(2);
-        if (w.expired()) return;
-      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    ring_put<64, 4>(r, my_tb % r.P, st.src_base + off, s, lane);
-    if (lane == 0)
-      *(GLOBAL uint64_t *)(r.entries + 8 * (my_tm % r.E)) = s | ((uint64_t)st.producer << 48);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    uint64_t my_tm = locking ? ld_rlx(rm_a) : tm;
+    uint64_t my_tb = locking ? ld_rlx(rb_a) : tb;
+    // wait until at least the first message fits, then take every leading
+    // message that fits in the room seen
+    uint64_t hm, hb;
+    const uint64_t s0 = shfl64(sz, 0);
+    for (;;) {
+      hm = shfl64(ld_rlx(hm_a), 0);  // one view of the consumer for the whole wave
+      hb = shfl64(ld_rlx(hb_a), 0);
+      if (my_tm - hm < r.E && my_tb - hb + s0 <= r.P) break;
+      __builtin_amdgcn_s_sleep(2);
+      if (w.expired()) return;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the consumer's reads are done
+    const bool fits = have && (my_tm + lane + 1 - hm <= r.E) && (my_tb + incl - hb <= r.P);
+    const uint64_t fm = __ballot(fits);
+    const uint32_t j = (uint32_t)__ffsll((unsigned long long)~fm) - 1;  // leading fitting lanes
+    const uint64_t bytes = shfl64(incl, (int)j - 1);
+    if (locking && lane == 0) {
+      st_rlx(rm_a, my_tm + j);
+      st_rlx(rb_a, my_tb + bytes);
+      st_rel(sv_a, ticket + 1);
+    }
+    // segments: message l of the batch -> ring bytes at (my_tb + excl_l) mod P
+    if (lane < j) {
+      const uint64_t pos = (my_tb + incl - sz) % r.P;
+      const uint64_t first = r.P - pos < sz ? r.P - pos : sz;
+      sg[2 * lane] = make_seg(r.payload + pos, st.src_base + off, first);
+      sg[2 * lane + 1] = make_seg(r.payload, st.src_base + off + first, sz - first);
+    }
+    wave_sync();
+    uint64_t nv = lane < 2 * j ? sg[lane].nv : 0;
+    const uint64_t nv_incl = wave_scan(nv, lane);
+    if (lane < 2 * j) sg[lane].v0 = nv_incl - nv;
+    const uint64_t total_v = shfl64(nv_incl, 63);
+    wave_sync();
+    seg_copy<64, 2>(sg, 2 * j, total_v, lane);
+    if (lane < j)
+      *(GLOBAL uint64_t *)(r.entries + 8 * ((my_tm + lane) % r.E)) =
+          sz | ((uint64_t)st.producer << 48);
     if (locking) {
-      while (ld_acq(tm_a) != my_tm) {  // publish in reservation order
+      // publish in reservation order, carrying the predecessors' writes
+      while (ld_rlx(tm_a) != my_tm) {
         __builtin_amdgcn_s_sleep(1);
         if (w.expired()) return;
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
-    if (lane == 0) {
-      if (a.ts_push) a.ts_push[st.first_msg + m] = wall_clock64();
-      st_rlx(tm_a, my_tm + 1);
-    }
-    tm = my_tm + 1;
-    tb = my_tb + s;
+    if (a.ts_push && lane < j) a.ts_push[st.first_msg + m + lane] = wall_clock64();
+    if (lane == 0) st_rlx(tm_a, my_tm + j);
+    wave_sync();
+    tm = my_tm + j;
+    tb = my_tb + bytes;
+    m += j;
     w.progress();
   }
 }
 
-// One consumer workgroup takes every message of one channel.
+// One consumer workgroup takes every message of one channel: each round it
+// looks at all of the channel's rings at once, takes up to kConsBatch
+// published messages (round robin over rings), copies them as one batch to
+// their streams' outputs and releases each ring's room with one store pair.
 __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
   __shared__ uint64_t s_hm[kMaxProducers], s_hb[kMaxProducers];
   __shared__ uint64_t s_outpos[kMaxProducers], s_cnt[kMaxProducers];
-  __shared__ uint64_t s_dst[kBatch], s_size[kBatch], s_pos[kBatch];
-  __shared__ uint32_t s_ring, s_k, s_stop;
+  __shared__ uint32_t s_take[kMaxProducers];
+  __shared__ uint64_t s_ent[kConsBatch];
+  __shared__ uint32_t s_ring_of[kConsBatch];
+  __shared__ uint64_t s_idx_of[kConsBatch];
+  __shared__ uint64_t s_rbytes[kMaxProducers];
+  __shared__ Seg s_seg[2 * kConsBatch];
+  __shared__ uint32_t s_k, s_stop, s_nseg;
+  __shared__ uint64_t s_total_v;
+  // per-ring and per-producer tables, staged once so the planning loop
+  // below touches LDS only
+  __shared__ uint64_t s_rpay[kMaxProducers], s_rent[kMaxProducers], s_rcoord[kMaxProducers];
+  __shared__ uint64_t s_pout[kMaxProducers], s_pbytes[kMaxProducers];
+  __shared__ uint64_t s_pfirst[kMaxProducers], s_pn[kMaxProducers];
+  __shared__ uint32_t s_psid[kMaxProducers];
   const DevChannel ch = a.chans[cid];
   const uint32_t lane = tid & 63, wave = tid >> 6;
+  const uint64_t P = a.rings[ch.first_ring].P, E = a.rings[ch.first_ring].E;
   for (uint32_t i = tid; i < ch.n_rings; i += kPumpBlock) {
-    const uint64_t c = a.rings[ch.first_ring + i].coord + offsetof(RingCoord, cons);
+    const DevRing rg = a.rings[ch.first_ring + i];
+    const uint64_t c = rg.coord + offsetof(RingCoord, cons);
     s_hm[i] = ld_acq(c);
     s_hb[i] = ld_acq(c + 8);
+    s_rpay[i] = rg.payload;
+    s_rent[i] = rg.entries;
+    s_rcoord[i] = rg.coord;
   }
   for (uint32_t p = tid; p < ch.K; p += kPumpBlock) {
+    const uint32_t sid = a.stream_of_prod[ch.prod_stream_base + p];
+    const DevStream so = a.streams[sid];
+    s_psid[p] = sid;
+    s_pout[p] = so.out_base;
+    s_pbytes[p] = so.out_bytes;
+    s_pfirst[p] = so.first_msg;
+    s_pn[p] = so.n_msgs;
     s_outpos[p] = 0;
     s_cnt[p] = 0;
   }
@@ -202,70 +337,87 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
   uint32_t rr = 0;
   while (done < ch.total_msgs) {
     if (wave == 0) {
-      // lanes probe rings rr, rr+1, ... in parallel; take the first with data
-      uint32_t ring = 0;
-      uint64_t avail = 0;
+      uint64_t av = 0;
+      uint32_t ri = 0;
+      bool stop = false;
       for (;;) {
-        uint64_t av = 0;
-        uint32_t ri = 0;
+        av = 0;
         if (lane < ch.n_rings) {
           ri = (rr + lane) % ch.n_rings;
-          const uint64_t c = a.rings[ch.first_ring + ri].coord;
-          av = ld_acq(c + offsetof(RingCoord, prod)) - s_hm[ri];
+          av = ld_rlx(s_rcoord[ri] + offsetof(RingCoord, prod)) - s_hm[ri];
         }
-        uint64_t m = __ballot(av > 0);
-        if (m) {
-          uint32_t f = (uint32_t)__ffsll((unsigned long long)m) - 1;
-          ring = (uint32_t)__shfl((int)ri, (int)f);
-          avail = ((uint64_t)__shfl((unsigned)(av >> 32), (int)f) << 32) |
-                  (uint64_t)__shfl((unsigned)av, (int)f);
-          break;
-        }
+        if (__ballot(av > 0)) break;
         __builtin_amdgcn_s_sleep(2);
         if (w.expired()) {
-          ring = ~0u;
+          stop = true;
           break;
         }
       }
+      // quotas in ring order starting at rr: take while the batch has room
+      const uint64_t left = ch.total_msgs - done;
+      const uint64_t cap = left < kConsBatch ? left : kConsBatch;
+      const uint64_t want = av < cap ? av : cap;
+      const uint64_t incl = wave_scan(want, lane);
+      uint64_t take = 0;
+      if (incl - want < cap) take = (incl <= cap) ? want : cap - (incl - want);
+      if (lane < ch.n_rings) s_take[ri] = (uint32_t)take;
+      const uint64_t k = shfl64(wave_scan(take, lane), 63);
       if (lane == 0) {
-        const uint64_t left = ch.total_msgs - done;
-        uint64_t k = avail < kBatch ? avail : kBatch;
-        if (k > left) k = left;
-        s_stop = ring == ~0u;
-        s_ring = ring;
+        s_stop = stop;
         s_k = (uint32_t)k;
       }
     }
     __syncthreads();
     if (s_stop) break;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const uint32_t ri = s_ring, k = s_k;
-    const DevRing r = a.rings[ch.first_ring + ri];
+    const uint32_t k = s_k;
+    // message i of the batch: ring and index within it (rings in order from rr)
     if (tid == 0) {
-      // entries are checked against the plan before any byte moves: a
+      uint32_t i = 0;
+      for (uint32_t q = 0; q < ch.n_rings && i < k; q++) {
+        const uint32_t ri = (rr + q) % ch.n_rings;
+        for (uint32_t x = 0; x < s_take[ri]; x++, i++) {
+          s_ring_of[i] = ri;
+          s_idx_of[i] = s_hm[ri] + x;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < k)
+      s_ent[tid] = *(const GLOBAL uint64_t *)(s_rent[s_ring_of[tid]] + 8 * (s_idx_of[tid] % E));
+    __syncthreads();
+    if (tid == 0) {
+      // plan the copies; entries are checked against the plan first, so a
       // malformed entry stops the pump instead of writing out of bounds
-      uint64_t pos = s_hb[ri] % r.P;
-      uint32_t bad = 0;
+      uint32_t bad = 0, nseg = 0;
+      for (uint32_t q = 0; q < ch.n_rings; q++) s_rbytes[q] = 0;
       for (uint32_t i = 0; i < k; i++) {
-        const uint64_t e = *(const GLOBAL uint64_t *)(r.entries + 8 * ((s_hm[ri] + i) % r.E));
+        const uint32_t ri = s_ring_of[i];
+        const uint64_t e = s_ent[i];
         const uint64_t sz = e & kEntrySizeMask;
         const uint32_t p = (uint32_t)(e >> 48) % ch.K;
-        const uint32_t sid = a.stream_of_prod[ch.prod_stream_base + p];
-        const DevStream &so = a.streams[sid];
-        if (sz > r.P || s_outpos[p] + sz > so.out_bytes || s_cnt[p] >= so.n_msgs) {
+        if (sz > P || s_outpos[p] + sz > s_pbytes[p] || s_cnt[p] >= s_pn[p]) {
           bad = 1;
-          s_size[i] = 0;
-          continue;
+          break;
         }
-        s_dst[i] = so.out_base + s_outpos[p];
-        s_size[i] = sz;
-        s_pos[i] = pos;
-        pos = (pos + sz) % r.P;
+        const uint64_t pos = (s_hb[ri] + s_rbytes[ri]) % P;
+        const uint64_t first = P - pos < sz ? P - pos : sz;
+        const uint64_t dst = s_pout[p] + s_outpos[p];
+        s_seg[nseg++] = make_seg(dst, s_rpay[ri] + pos, first);
+        if (sz > first) s_seg[nseg++] = make_seg(dst + first, s_rpay[ri], sz - first);
+        s_rbytes[ri] += sz;
         s_outpos[p] += sz;
-        if (a.trace) a.trace[ch.trace_base + done + i] = sid;
-        if (a.ts_pop) a.ts_pop[so.first_msg + s_cnt[p]] = wall_clock64();
+        if (a.trace) a.trace[ch.trace_base + done + i] = s_psid[p];
+        if (a.ts_pop) a.ts_pop[s_pfirst[p] + s_cnt[p]] = wall_clock64();
         s_cnt[p] += 1;
       }
+      uint64_t v = 0;
+      for (uint32_t g = 0; g < nseg; g++) {
+        s_seg[g].v0 = v;
+        v += s_seg[g].nv;
+      }
+      s_nseg = nseg;
+      s_total_v = v;
       if (bad) {
         __hip_atomic_fetch_or(&a.err[0], kErrCorrupt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_stop = 1;
@@ -273,33 +425,35 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
     }
     __syncthreads();
     if (s_stop) break;
-    uint64_t bytes = 0;
-    for (uint32_t i = 0; i < k; i++) {
-      ring_get<kPumpBlock, 4>(r, s_pos[i], s_dst[i], s_size[i], tid);
-      bytes += s_size[i];
-    }
-    __syncthreads();  // every read of the ring has completed
+    seg_copy<kPumpBlock, 4>(s_seg, s_nseg, s_total_v, tid);
+    __syncthreads();  // every read of the rings has completed
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const uint64_t c = r.coord + offsetof(RingCoord, cons);
-      st_rlx(c + 8, s_hb[ri] + bytes);
-      st_rlx(c, s_hm[ri] + k);
-      s_hm[ri] += k;
-      s_hb[ri] += bytes;
+      for (uint32_t q = 0; q < ch.n_rings; q++) {
+        const uint32_t t = s_take[q];
+        if (!t) continue;
+        const uint64_t c = s_rcoord[q] + offsetof(RingCoord, cons);
+        s_hb[q] += s_rbytes[q];
+        s_hm[q] += t;
+        st_rlx(c + 8, s_hb[q]);
+        st_rlx(c, s_hm[q]);
+      }
     }
     done += k;
-    rr = (ri + 1) % ch.n_rings;
+    rr = (rr + 1) % ch.n_rings;
     w.progress();
   }
   __threadfence();
 }
 
-__global__ __launch_bounds__(kPumpBlock) void pump_kernel(PumpArgs a) {
+__global__ __launch_bounds__(kPumpBlock) __attribute__((amdgpu_waves_per_eu(6, 8)))
+void pump_kernel(PumpArgs a) {
   const DevRole role = a.roles[blockIdx.x];
   const uint32_t tid = threadIdx.x;
+  __shared__ Seg s_pseg[4][2 * kProdBatch];
   if (role.kind == 0) {
     const uint32_t wave = tid >> 6;
-    if (wave < role.count) run_producer(a, role.ids[wave], tid & 63);
+    if (wave < role.count) run_producer(a, role.ids[wave], tid & 63, s_pseg[wave]);
     __threadfence();
   } else {
     run_consumer(a, role.ids[0], tid);

@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
     is_last = (prev == gridDim.x - 1) ? 1u : 0u;
   }
   __syncthreads();
-  if (is_last) {
+  if (is_last && counters) {
     __threadfence();
     for (uint32_t i = tid; i < n; i += kCopyBlock) {
       const uint64_t sp = b.slots[i];
@@ -174,8 +174,9 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
       __hip_atomic_fetch_add(&counters[2 * dslot + 1], 1ull, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (tid == 0) __hip_atomic_store(grid_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (is_last && tid == 0)
+    __hip_atomic_store(grid_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 hipError_t launch_copy(const DevBatch &b, DevSched s, const DevSched *sched_dev,

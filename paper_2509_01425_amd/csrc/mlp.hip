@@ -1,0 +1,210 @@
+// mlp.hip -- the schedule-predicting network on gfx950: 32 -> 64 -> 64 -> 12,
+// ReLU, softmax cross-entropy, Adam (Kingma & Ba 2015), all fp32.
+//
+// The network is tiny (7,052 parameters, ~14 kFLOP per sample), so each
+// kernel gives one thread one output element and sums in a fixed order: the
+// results are deterministic run to run.  Parameter layout (flat, row-major):
+// W1[64,32] b1[64] W2[64,64] b2[64] W3[12,64] b3[12].
+//
+// sched_infer_kernel runs inside a memcpy submission: one workgroup builds
+// the batch's 32-bin log2 size histogram in LDS, evaluates the network on
+// log2(1 + count) and writes the argmax class's schedule for the copy kernel
+// that follows on the same stream.
+#include "internal.h"
+#include "mlp.h"
+
+namespace hicr {
+
+__global__ __launch_bounds__(256) void dense_fwd_kernel(const float *X, const float *W,
+                                                        const float *bias, int I, int O, int B,
+                                                        float *Ypre, float *Yact) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= B * O) return;
+  const int b = t / O, o = t % O;
+  float acc = bias[o];
+  for (int i = 0; i < I; i++) acc = fmaf(W[o * I + i], X[b * I + i], acc);
+  Ypre[t] = acc;
+  if (Yact) Yact[t] = acc > 0.f ? acc : 0.f;
+}
+
+// Per sample: softmax of the logits, dZ = (p - onehot(y)) / B, and the
+// sample's cross-entropy log-sum-exp(z) - z_y.
+__global__ __launch_bounds__(256) void softmax_xent_kernel(const float *Z, const int32_t *y,
+                                                           int B, float *dZ, float *loss) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const float *z = Z + b * kMlpOut;
+  float m = z[0];
+  for (int c = 1; c < kMlpOut; c++) m = fmaxf(m, z[c]);
+  float sum = 0.f;
+  for (int c = 0; c < kMlpOut; c++) sum += expf(z[c] - m);
+  const int yb = y[b];
+  for (int c = 0; c < kMlpOut; c++) {
+    const float p = expf(z[c] - m) / sum;
+    dZ[b * kMlpOut + c] = (p - (c == yb ? 1.f : 0.f)) / (float)B;
+  }
+  if (loss) loss[b] = (m + logf(sum)) - z[yb];
+}
+
+// dX[b,i] = (sum_o dY[b,o] W[o,i]) * [Xpre[b,i] > 0]
+__global__ __launch_bounds__(256) void dense_bwd_input_kernel(const float *dY, const float *W,
+                                                              const float *Xpre, int I, int O,
+                                                              int B, float *dX) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= B * I) return;
+  const int b = t / I, i = t % I;
+  float acc = 0.f;
+  for (int o = 0; o < O; o++) acc = fmaf(dY[b * O + o], W[o * I + i], acc);
+  dX[t] = Xpre[t] > 0.f ? acc : 0.f;
+}
+
+// dW[o,i] = sum_b dY[b,o] X[b,i]; thread (o, I) computes db[o] = sum_b dY[b,o].
+__global__ __launch_bounds__(256) void dense_bwd_weight_kernel(const float *dY, const float *X,
+                                                               int I, int O, int B, float *dW,
+                                                               float *db) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= O * (I + 1)) return;
+  const int o = t / (I + 1), i = t % (I + 1);
+  float acc = 0.f;
+  if (i < I) {
+    for (int b = 0; b < B; b++) acc = fmaf(dY[b * O + o], X[b * I + i], acc);
+    dW[o * I + i] = acc;
+  } else {
+    for (int b = 0; b < B; b++) acc += dY[b * O + o];
+    db[o] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void mean_kernel(const float *v, int n, float *out) {
+  __shared__ float part[256];
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int i = 0; i < 256; i++) s += part[i];
+    *out = s / (float)n;
+  }
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float *p, const float *g, float *m, float *v,
+                                                   int n, float lr, float b1, float b2, float eps,
+                                                   float bc1, float bc2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// Histogram bin of a request size: floor(log2 s) capped at 31; size 0 -> 0.
+__device__ __forceinline__ int size_bin(uint64_t s) {
+  if (s == 0) return 0;
+  const int b = 63 - __clzll((long long)s);
+  return b > 31 ? 31 : b;
+}
+
+__global__ __launch_bounds__(256) void sched_infer_kernel(const uint64_t *sizes, uint32_t n,
+                                                          const float *params,
+                                                          const DevSched *classes,
+                                                          DevSched *out) {
+  __shared__ uint32_t hist[kMlpIn];
+  __shared__ float x[kMlpIn], h1[kMlpHidden], h2[kMlpHidden], z[kMlpOut];
+  const int t = threadIdx.x;
+  if (t < kMlpIn) hist[t] = 0;
+  __syncthreads();
+  for (uint32_t i = t; i < n; i += 256) atomicAdd(&hist[size_bin(sizes[i])], 1u);
+  __syncthreads();
+  if (t < kMlpIn) x[t] = log2f(1.f + (float)hist[t]);
+  __syncthreads();
+  const float *W1 = params, *b1 = W1 + kMlpHidden * kMlpIn, *W2 = b1 + kMlpHidden,
+              *b2 = W2 + kMlpHidden * kMlpHidden, *W3 = b2 + kMlpHidden,
+              *b3 = W3 + kMlpOut * kMlpHidden;
+  if (t < kMlpHidden) {
+    float a = b1[t];
+    for (int i = 0; i < kMlpIn; i++) a = fmaf(W1[t * kMlpIn + i], x[i], a);
+    h1[t] = a > 0.f ? a : 0.f;
+  }
+  __syncthreads();
+  if (t < kMlpHidden) {
+    float a = b2[t];
+    for (int i = 0; i < kMlpHidden; i++) a = fmaf(W2[t * kMlpHidden + i], h1[i], a);
+    h2[t] = a > 0.f ? a : 0.f;
+  }
+  __syncthreads();
+  if (t < kMlpOut) {
+    float a = b3[t];
+    for (int i = 0; i < kMlpHidden; i++) a = fmaf(W3[t * kMlpHidden + i], h2[i], a);
+    z[t] = a;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int best = 0;
+    for (int c = 1; c < kMlpOut; c++)
+      if (z[c] > z[best]) best = c;  // ties go to the lowest class
+    DevSched s = classes[best];
+    s.cls = (uint32_t)best;
+    *out = s;
+  }
+}
+
+static inline unsigned blocks(int n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t mlp_forward(const MlpBufs &m, const float *params, const float *X, int B,
+                       hipStream_t s) {
+  const float *W1 = params, *b1 = W1 + kMlpHidden * kMlpIn, *W2 = b1 + kMlpHidden,
+              *b2 = W2 + kMlpHidden * kMlpHidden, *W3 = b2 + kMlpHidden,
+              *b3 = W3 + kMlpOut * kMlpHidden;
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks(B * kMlpHidden)), dim3(256), 0, s, X, W1, b1,
+                     kMlpIn, kMlpHidden, B, m.a1, m.h1);
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks(B * kMlpHidden)), dim3(256), 0, s, m.h1, W2,
+                     b2, kMlpHidden, kMlpHidden, B, m.a2, m.h2);
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks(B * kMlpOut)), dim3(256), 0, s, m.h2, W3, b3,
+                     kMlpHidden, kMlpOut, B, m.z, (float *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t mlp_backward(const MlpBufs &m, const float *params, const float *X, const int32_t *y,
+                        int B, float *grad, float *loss_mean, hipStream_t s) {
+  const float *W2 = params + kMlpHidden * kMlpIn + kMlpHidden;
+  const float *W3 = W2 + kMlpHidden * kMlpHidden + kMlpHidden;
+  float *gW1 = grad, *gb1 = gW1 + kMlpHidden * kMlpIn, *gW2 = gb1 + kMlpHidden,
+        *gb2 = gW2 + kMlpHidden * kMlpHidden, *gW3 = gb2 + kMlpHidden,
+        *gb3 = gW3 + kMlpOut * kMlpHidden;
+  hipLaunchKernelGGL(softmax_xent_kernel, dim3(blocks(B)), dim3(256), 0, s, m.z, y, B, m.dz,
+                     m.loss);
+  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(blocks(kMlpOut * (kMlpHidden + 1))), dim3(256),
+                     0, s, m.dz, m.h2, kMlpHidden, kMlpOut, B, gW3, gb3);
+  hipLaunchKernelGGL(dense_bwd_input_kernel, dim3(blocks(B * kMlpHidden)), dim3(256), 0, s, m.dz,
+                     W3, m.a2, kMlpHidden, kMlpOut, B, m.d2);
+  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(blocks(kMlpHidden * (kMlpHidden + 1))),
+                     dim3(256), 0, s, m.d2, m.h1, kMlpHidden, kMlpHidden, B, gW2, gb2);
+  hipLaunchKernelGGL(dense_bwd_input_kernel, dim3(blocks(B * kMlpHidden)), dim3(256), 0, s, m.d2,
+                     W2, m.a1, kMlpHidden, kMlpHidden, B, m.d1);
+  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(blocks(kMlpHidden * (kMlpIn + 1))), dim3(256),
+                     0, s, m.d1, X, kMlpIn, kMlpHidden, B, gW1, gb1);
+  if (loss_mean) hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, m.loss, B, loss_mean);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(float *p, const float *g, float *mo, float *ve, float lr, int t,
+                    hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks(kMlpParams)), dim3(256), 0, s, p, g, mo, ve,
+                     kMlpParams, lr, b1, b2, 1e-8f, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_sched_infer(const uint64_t *sizes, uint32_t n, const float *params,
+                              const DevSched *classes, DevSched *out, hipStream_t s) {
+  hipLaunchKernelGGL(sched_infer_kernel, dim3(1), dim3(256), 0, s, sizes, n, params, classes,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace hicr

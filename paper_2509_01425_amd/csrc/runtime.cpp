@@ -139,8 +139,8 @@ int ensure_counter_capacity(hicr_ctx c, uint32_t nslots) {
 }
 
 // Validate, pack and launch n requests as one submission.
-int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
-           const DevSched *sched_dev, hipStream_t stream, uint64_t *bad) {
+int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, bool learned,
+           hipStream_t stream, uint64_t *bad, const SubmitOpts *opt) {
   for (uint64_t i = 0; i < n; i++) {
     int rc = check_desc(c, d[i]);
     if (rc != HICR_OK) {
@@ -168,6 +168,19 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
   if (e != hipSuccess) return hip_fail(c, e, "uploading a batch");
   const uint64_t *dd = static_cast<const uint64_t *>(s.d);
   DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
+  const DevSched *sched_dev = nullptr;
+  if (learned) {
+    // the network picks the class on the device, from the uploaded sizes
+    e = sched_infer(c, dd + 2 * n, n, s.sched_dev, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launching schedule inference");
+    sched_dev = s.sched_dev;
+    c->last_learned_sub = (int)(&s - c->subs);
+  }
+  uint64_t *counters = (opt && opt->no_count) ? nullptr : c->d_counters;
+  if (opt && opt->t0) {
+    e = hipEventRecord(opt->t0, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
+  }
   // With a device-side choice the host does not know the chunk; bound the
   // piece count with the smallest chunk of any class.
   const uint32_t bound_chunk = sched_dev ? kChunks[0] : sched.chunk_bytes;
@@ -187,9 +200,13 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
                   (unsigned long long)i0);
     DevBatch b{dd + i0, dd + n + i0, dd + 2 * n + i0, dd + 3 * n + i0, (uint32_t)(i1 - i0)};
     uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(pieces, 1), cap_grid);
-    e = launch_copy(b, ds, sched_dev, c->d_counters, s.grid_done, grid, stream);
+    e = launch_copy(b, ds, sched_dev, counters, s.grid_done, grid, stream);
     if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
     i0 = i1;
+  }
+  if (opt && opt->t1) {
+    e = hipEventRecord(opt->t1, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
   }
   e = hipEventRecord(s.ev, stream);
   if (e != hipSuccess) return hip_fail(c, e, "recording a batch event");
@@ -202,7 +219,7 @@ int flush_pending(hicr_ctx c) {
   std::vector<hicr_desc> p;
   p.swap(c->pending);
   uint64_t bad = 0;
-  return submit(c, p.data(), p.size(), c->def_sched, nullptr, c->stream, &bad);
+  return submit(c, p.data(), p.size(), c->def_sched, false, c->stream, &bad, nullptr);
 }
 
 }  // namespace hicr
@@ -279,6 +296,7 @@ int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
   for (int i = 0; ok && i < kNumSubs; i++) {
     ok = hipEventCreateWithFlags(&c->subs[i].ev, hipEventDisableTiming) == hipSuccess;
     c->subs[i].grid_done = reinterpret_cast<uint32_t *>(c->d_words + 64 * i);
+    c->subs[i].sched_dev = reinterpret_cast<DevSched *>(c->d_words + 64 * i + 16);
   }
   c->def_sched = hicr_sched{64u << 10, 1, 2, HICR_SCHED_FIXED};
   if (!ok || ensure_counter_capacity(c, 1024) != HICR_OK) {
@@ -406,10 +424,9 @@ int hicr_memcpy_batch(hicr_ctx c, const hicr_desc *descs, uint64_t n, const hicr
   std::lock_guard<std::mutex> g(c->mu);
   (void)hipSetDevice(c->device);
   hicr_sched sched = s ? *s : c->def_sched;
-  const DevSched *sched_dev = nullptr;
+  bool learned = false;
   if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
-    int rc = choose_sched(c, descs, n, sched.mode, &sched, &sched_dev,
-                          stream ? static_cast<hipStream_t>(stream) : c->stream);
+    int rc = choose_sched(c, descs, n, sched.mode, &sched, &learned);
     if (rc != HICR_OK) return rc;
   } else if (sched.mode != HICR_SCHED_FIXED) {
     return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
@@ -418,8 +435,8 @@ int hicr_memcpy_batch(hicr_ctx c, const hicr_desc *descs, uint64_t n, const hicr
   if (rc != HICR_OK) return rc;
   rc = flush_pending(c);
   if (rc != HICR_OK) return rc;
-  return submit(c, descs, n, sched, sched_dev,
-                stream ? static_cast<hipStream_t>(stream) : c->stream, bad);
+  return submit(c, descs, n, sched, learned,
+                stream ? static_cast<hipStream_t>(stream) : c->stream, bad, nullptr);
 }
 
 int hicr_fence(hicr_ctx c) {

@@ -30,6 +30,14 @@ struct Sub {
   hipEvent_t ev = nullptr;
   bool inflight = false;
   uint32_t *grid_done = nullptr;
+  DevSched *sched_dev = nullptr;  // schedule chosen on the device (learned mode)
+};
+
+// Extra controls of one submission (autotuner).
+struct SubmitOpts {
+  bool no_count = false;     // do not raise slot counters
+  hipEvent_t t0 = nullptr;   // recorded just before the first copy launch
+  hipEvent_t t1 = nullptr;   // recorded just after the last copy launch
 };
 
 constexpr int kNumSubs = 4;
@@ -67,10 +75,11 @@ struct hicr_ctx_s {
   std::vector<hicr_desc> pending;
   hicr_sched def_sched{};
   hicr::SchedState *sched = nullptr;
+  int last_learned_sub = -1;  // submission whose class the device chose last
   std::vector<struct hicr_channel_s *> channels;
   std::vector<hicr::Extra> extra;
   int pump_occ = 0;  // pump workgroups per CU
-  hipEvent_t push_ev = nullptr;  // last host-API channel push
+  hipEvent_t push_ev = nullptr;  // last host-API channel push or network step
   bool push_pending = false;
   std::mutex abort_mu;  // guards abort_words; never held while waiting on the GPU
   std::vector<uint32_t *> abort_words;
@@ -86,17 +95,31 @@ int check_desc(hicr_ctx c, const hicr_desc &d);
 int check_sched(hicr_ctx c, const hicr_sched &s);
 bool any_inflight(hicr_ctx c);
 int wait_all(hicr_ctx c);
-int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
-           const DevSched *sched_dev, hipStream_t stream, uint64_t *bad);
+int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, bool learned,
+           hipStream_t stream, uint64_t *bad, const SubmitOpts *opt);
 int flush_pending(hicr_ctx c);
 int ensure_counter_capacity(hicr_ctx c, uint32_t nslots);
 
-// Schedule selection (sched.cpp).
+// Schedule selection (sched.cpp).  For mode LEARNED with a loaded network
+// *learned is set and the class is picked on the device during submission.
 int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out,
-                 const DevSched **sched_dev, hipStream_t stream);
+                 bool *learned);
+hipError_t sched_infer(hicr_ctx c, const uint64_t *sizes_dev, uint64_t n, DevSched *out,
+                       hipStream_t stream);
 void destroy_sched(hicr_ctx c);
 
 // Channel pushes and pumps (channel.cpp).
+struct PumpStream {
+  struct ::hicr_channel_s *channel;
+  uint32_t producer;
+  uint64_t src_base, src_size, out_base, out_size;
+  uint64_t first_msg, n_msgs;
+};
+int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *msg_off,
+                const uint64_t *msg_size, uint64_t n_msgs, uint32_t *trace_dev, uint64_t *ts_dev,
+                uint64_t timeout_ns, hipStream_t s, Extra *xout);
+int pump_finish(hicr_ctx c, Extra &x);
+uint64_t channel_payload_limit(struct ::hicr_channel_s *ch);
 int wait_extra(hicr_ctx c);
 bool extra_inflight(hicr_ctx c);
 void destroy_extra(hicr_ctx c);

@@ -1,18 +1,330 @@
-// sched.cpp -- schedule selection for a batch (fixed / autotuned / learned).
+// sched.cpp -- choosing a batch's copy schedule: the autotuner (times every
+// class on a batch), the tuned table (nearest autotuned batch by histogram
+// feature), and the device-resident network (trained by the project's own
+// HIP kernels, evaluated inside the submission).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mlp.h"
 #include "runtime.h"
 
 namespace hicr {
 
-struct SchedState {};
+struct SchedState {
+  float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
+  float *d_loss = nullptr;
+  int step = 0;
+  bool net_loaded = false;
+  float *d_act = nullptr;  // activations of up to act_cap samples
+  int act_cap = 0;
+  MlpBufs bufs{};
+  DevSched *d_classes = nullptr;  // the 12 class schedules
+  std::vector<std::array<float, kMlpIn>> feats;  // tuned table
+  std::vector<uint32_t> cls;
+};
 
-int choose_sched(hicr_ctx c, const hicr_desc *, uint64_t, uint32_t mode, hicr_sched *,
-                 const DevSched **, hipStream_t) {
-  return fail(c, HICR_EINVAL, "schedule mode %u is not available on this context", mode);
+void batch_features(const uint64_t *sizes, uint64_t n, size_t stride, float *out) {
+  uint64_t cnt[kMlpIn] = {0};
+  const char *p = reinterpret_cast<const char *>(sizes);
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t s;
+    std::memcpy(&s, p + i * stride, 8);
+    int b = s == 0 ? 0 : 63 - __builtin_clzll(s);
+    cnt[b > 31 ? 31 : b]++;
+  }
+  for (int b = 0; b < kMlpIn; b++) out[b] = std::log2(1.0f + (float)cnt[b]);
+}
+
+static int state(hicr_ctx c, SchedState **out) {
+  if (!c->sched) {
+    SchedState *s = new (std::nothrow) SchedState();
+    if (!s) return HICR_ENOMEM;
+    const size_t pb = sizeof(float) * kMlpParams;
+    bool ok = hipMalloc(&s->d_params, pb) == hipSuccess && hipMalloc(&s->d_m, pb) == hipSuccess &&
+              hipMalloc(&s->d_v, pb) == hipSuccess && hipMalloc(&s->d_grad, pb) == hipSuccess &&
+              hipMalloc(&s->d_loss, 64) == hipSuccess &&
+              hipMalloc(&s->d_classes, sizeof(DevSched) * kMlpOut) == hipSuccess;
+    if (ok) {
+      DevSched cl[kMlpOut];
+      for (uint32_t k = 0; k < (uint32_t)kMlpOut; k++) {
+        hicr_sched h;
+        hicr_sched_class(k, &h);
+        cl[k] = DevSched{h.chunk_bytes, h.wgs_per_desc, h.unroll, k};
+      }
+      ok = hipMemcpy(s->d_classes, cl, sizeof cl, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    c->sched = s;
+    if (!ok) return fail(c, HICR_ENOMEM, "network state");
+  }
+  *out = c->sched;
+  return HICR_OK;
+}
+
+static int ensure_act(hicr_ctx c, SchedState *s, int B) {
+  if (B <= s->act_cap) return HICR_OK;
+  if (s->d_act) (void)hipFree(s->d_act);
+  s->d_act = nullptr;
+  s->act_cap = 0;
+  const size_t per = 2 * kMlpHidden * 2 + kMlpOut * 2 + kMlpHidden * 2 + 1;  // floats/sample
+  if (hipMalloc(&s->d_act, sizeof(float) * per * B) != hipSuccess)
+    return fail(c, HICR_ENOMEM, "activations for %d samples", B);
+  float *p = s->d_act;
+  auto take = [&](int n) { float *q = p; p += (size_t)n * B; return q; };
+  s->bufs.a1 = take(kMlpHidden);
+  s->bufs.h1 = take(kMlpHidden);
+  s->bufs.a2 = take(kMlpHidden);
+  s->bufs.h2 = take(kMlpHidden);
+  s->bufs.z = take(kMlpOut);
+  s->bufs.dz = take(kMlpOut);
+  s->bufs.d2 = take(kMlpHidden);
+  s->bufs.d1 = take(kMlpHidden);
+  s->bufs.loss = take(1);
+  s->act_cap = B;
+  return HICR_OK;
+}
+
+static uint32_t nearest(const SchedState *s, const float *f) {
+  uint32_t best = 0;
+  float bd = 3.4e38f;
+  for (size_t k = 0; k < s->feats.size(); k++) {
+    float d = 0.f;
+    for (int b = 0; b < kMlpIn; b++) {
+      const float x = s->feats[k][b] - f[b];
+      d += x * x;
+    }
+    if (d < bd) {
+      bd = d;
+      best = s->cls[k];
+    }
+  }
+  return best;
+}
+
+int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out,
+                 bool *learned) {
+  *learned = false;
+  SchedState *s = c->sched;
+  if (mode == HICR_SCHED_LEARNED && s && s->net_loaded) {
+    *learned = true;
+    *out = c->def_sched;  // placeholder for host-side validation
+    return HICR_OK;
+  }
+  // tuned table, the fallback when no network is loaded; default if empty
+  if (s && !s->feats.empty() && n) {
+    float f[kMlpIn];
+    batch_features(&d[0].size, n, sizeof(hicr_desc), f);
+    return hicr_sched_class(nearest(s, f), out);
+  }
+  *out = c->def_sched;
+  return HICR_OK;
+}
+
+hipError_t sched_infer(hicr_ctx c, const uint64_t *sizes_dev, uint64_t n, DevSched *out,
+                       hipStream_t stream) {
+  return launch_sched_infer(sizes_dev, (uint32_t)n, c->sched->d_params, c->sched->d_classes, out,
+                            stream);
 }
 
 void destroy_sched(hicr_ctx c) {
-  delete c->sched;
+  SchedState *s = c->sched;
+  if (!s) return;
+  for (void *p : {(void *)s->d_params, (void *)s->d_m, (void *)s->d_v, (void *)s->d_grad,
+                  (void *)s->d_loss, (void *)s->d_act, (void *)s->d_classes})
+    if (p) (void)hipFree(p);
+  delete s;
   c->sched = nullptr;
 }
 
 }  // namespace hicr
+
+using namespace hicr;
+
+extern "C" {
+
+int hicr_sched_features(const hicr_desc *descs, uint64_t n, float *out32) {
+  if (!out32 || (n && !descs)) return HICR_EINVAL;
+  if (n == 0) {
+    for (int b = 0; b < kMlpIn; b++) out32[b] = 0.f;
+    return HICR_OK;
+  }
+  batch_features(&descs[0].size, n, sizeof(hicr_desc), out32);
+  return HICR_OK;
+}
+
+int hicr_mlp_set_params(hicr_ctx c, const float *params) {
+  if (!c || !params) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  int rc = wait_all(c);
+  if (rc != HICR_OK) return rc;
+  SchedState *s;
+  rc = state(c, &s);
+  if (rc != HICR_OK) return rc;
+  const size_t pb = sizeof(float) * kMlpParams;
+  hipError_t e = hipMemcpy(s->d_params, params, pb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(s->d_m, 0, pb);
+  if (e == hipSuccess) e = hipMemset(s->d_v, 0, pb);
+  if (e != hipSuccess) return hip_fail(c, e, "loading network parameters");
+  s->step = 0;
+  s->net_loaded = true;
+  return HICR_OK;
+}
+
+int hicr_mlp_get_params(hicr_ctx c, float *out) {
+  if (!c || !out) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
+  (void)hipSetDevice(c->device);
+  int rc = wait_all(c);
+  if (rc != HICR_OK) return rc;
+  hipError_t e = hipMemcpy(out, c->sched->d_params, sizeof(float) * kMlpParams,
+                           hipMemcpyDeviceToHost);
+  return e == hipSuccess ? HICR_OK : hip_fail(c, e, "reading network parameters");
+}
+
+int hicr_mlp_forward(hicr_ctx c, const float *x_dev, uint32_t batch, float *logits_dev) {
+  if (!c || !x_dev || !logits_dev || batch == 0) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
+  (void)hipSetDevice(c->device);
+  SchedState *s = c->sched;
+  int rc = ensure_act(c, s, (int)batch);
+  if (rc != HICR_OK) return rc;
+  hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(logits_dev, s->bufs.z, sizeof(float) * kMlpOut * batch,
+                       hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e == hipSuccess ? HICR_OK : hip_fail(c, e, "network forward");
+}
+
+int hicr_mlp_grad(hicr_ctx c, const float *x_dev, const int32_t *y_dev, uint32_t batch,
+                  float *grad_dev, float *loss_dev) {
+  if (!c || !x_dev || !y_dev || !grad_dev || batch == 0) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
+  (void)hipSetDevice(c->device);
+  SchedState *s = c->sched;
+  int rc = ensure_act(c, s, (int)batch);
+  if (rc != HICR_OK) return rc;
+  hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
+  if (e == hipSuccess)
+    e = mlp_backward(s->bufs, s->d_params, x_dev, y_dev, (int)batch, grad_dev, loss_dev,
+                     c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e == hipSuccess ? HICR_OK : hip_fail(c, e, "network gradient");
+}
+
+int hicr_mlp_train_step(hicr_ctx c, const float *x_dev, const int32_t *y_dev, uint32_t batch,
+                        float lr, float *loss_dev) {
+  if (!c || !x_dev || !y_dev || batch == 0 || !(lr > 0.f)) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
+  (void)hipSetDevice(c->device);
+  SchedState *s = c->sched;
+  int rc = ensure_act(c, s, (int)batch);
+  if (rc != HICR_OK) return rc;
+  hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
+  if (e == hipSuccess)
+    e = mlp_backward(s->bufs, s->d_params, x_dev, y_dev, (int)batch, s->d_grad, loss_dev,
+                     c->stream);
+  if (e == hipSuccess) e = mlp_adam(s->d_params, s->d_grad, s->d_m, s->d_v, lr, ++s->step, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(c->push_ev, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "network training step");
+  c->push_pending = true;
+  return HICR_OK;
+}
+
+int hicr_last_choice(hicr_ctx c, uint32_t *cls) {
+  if (!c || !cls) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (c->last_learned_sub < 0) return fail(c, HICR_EINVAL, "no learned submission yet");
+  (void)hipSetDevice(c->device);
+  Sub &s = c->subs[c->last_learned_sub];
+  hipError_t e = hipEventSynchronize(s.ev);
+  DevSched d{};
+  if (e == hipSuccess) e = hipMemcpy(&d, s.sched_dev, sizeof d, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the chosen class");
+  *cls = d.cls;
+  return HICR_OK;
+}
+
+int hicr_tune_add(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t cls) {
+  if (!c || (n && !descs) || cls >= HICR_NUM_CLASSES) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  SchedState *s;
+  int rc = state(c, &s);
+  if (rc != HICR_OK) return rc;
+  std::array<float, kMlpIn> f{};
+  if (n) batch_features(&descs[0].size, n, sizeof(hicr_desc), f.data());
+  s->feats.push_back(f);
+  s->cls.push_back(cls);
+  return HICR_OK;
+}
+
+int hicr_tune_clear(hicr_ctx c) {
+  if (!c) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (c->sched) {
+    c->sched->feats.clear();
+    c->sched->cls.clear();
+  }
+  return HICR_OK;
+}
+
+int hicr_autotune(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t reps, float *times_ms,
+                  uint32_t *best) {
+  if (!c || !descs || n == 0 || reps == 0 || reps > 64 || !times_ms) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  int rc = flush_pending(c);
+  if (rc == HICR_OK) rc = wait_all(c);
+  if (rc != HICR_OK) return rc;
+  hipEvent_t t0[64], t1[64];
+  for (uint32_t r = 0; r < reps; r++) {
+    if (hipEventCreate(&t0[r]) != hipSuccess || hipEventCreate(&t1[r]) != hipSuccess)
+      return fail(c, HICR_EDEVICE, "timing events");
+  }
+  uint64_t bad = 0;
+  for (uint32_t k = 0; k < (uint32_t)HICR_NUM_CLASSES && rc == HICR_OK; k++) {
+    hicr_sched sch;
+    hicr_sched_class(k, &sch);
+    SubmitOpts warm;
+    warm.no_count = true;
+    rc = submit(c, descs, n, sch, false, c->stream, &bad, &warm);
+    std::vector<float> ms(reps);
+    for (uint32_t r = 0; r < reps && rc == HICR_OK; r++) {
+      SubmitOpts o;
+      o.no_count = true;
+      o.t0 = t0[r];
+      o.t1 = t1[r];
+      rc = submit(c, descs, n, sch, false, c->stream, &bad, &o);
+    }
+    if (rc == HICR_OK) rc = wait_all(c);
+    for (uint32_t r = 0; r < reps && rc == HICR_OK; r++)
+      if (hipEventElapsedTime(&ms[r], t0[r], t1[r]) != hipSuccess)
+        rc = fail(c, HICR_EDEVICE, "reading timing events");
+    if (rc == HICR_OK) {
+      std::sort(ms.begin(), ms.end());
+      times_ms[k] = ms[reps / 2];
+    }
+  }
+  for (uint32_t r = 0; r < reps; r++) {
+    (void)hipEventDestroy(t0[r]);
+    (void)hipEventDestroy(t1[r]);
+  }
+  if (rc != HICR_OK) return rc;
+  if (best) {
+    uint32_t b = 0;
+    for (uint32_t k = 1; k < (uint32_t)HICR_NUM_CLASSES; k++)
+      if (times_ms[k] < times_ms[b]) b = k;  // ties go to the lowest class
+    *best = b;
+  }
+  return HICR_OK;
+}
+
+}  // extern "C"

@@ -74,6 +74,36 @@ class hicr_pump_io(ctypes.Structure):
                 ("ts_dev", ctypes.c_void_p), ("timeout_ns", ctypes.c_uint64)]
 
 
+REQ_COPY, REQ_BURST = 0, 1
+
+
+class hicr_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("channel", ctypes.c_uint32),
+                ("first", ctypes.c_uint64), ("count", ctypes.c_uint64),
+                ("hbm_bytes", ctypes.c_uint64), ("arrival_ns", ctypes.c_uint64)]
+
+
+ON_COMPLETE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
+
+
+class hicr_serve_cfg(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_uint32), ("src", ctypes.c_uint32),
+                ("streams", ctypes.c_uint32), ("max_batch_reqs", ctypes.c_uint32),
+                ("descs", ctypes.c_void_p), ("n_descs", ctypes.c_uint64),
+                ("msg_src_off", ctypes.c_void_p), ("msg_size", ctypes.c_void_p),
+                ("n_msgs", ctypes.c_uint64), ("channels", ctypes.c_void_p),
+                ("n_channels", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("sched_or_null", ctypes.c_void_p), ("on_complete", ON_COMPLETE),
+                ("user", ctypes.c_void_p), ("admit_ns", ctypes.c_void_p),
+                ("done_ns", ctypes.c_void_p)]
+
+
+class hicr_serve_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("peak_arena_bytes", ctypes.c_uint64),
+                ("copy_launches", ctypes.c_uint64), ("pump_launches", ctypes.c_uint64),
+                ("max_inflight_requests", ctypes.c_uint64), ("wall_ns", ctypes.c_uint64)]
+
+
 _u32, _u64, _vp, _int = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
 _pu32, _pu64, _pvp = ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_vp)
 
@@ -100,6 +130,18 @@ _SIGNATURES = {
     "hicr_channel_pump": (_int, [_vp, ctypes.POINTER(hicr_stream), _u32,
                                  ctypes.POINTER(hicr_pump_io), _vp]),
     "hicr_channel_abort": (_int, [_vp]),
+    "hicr_sched_features": (_int, [_vp, _u64, _vp]),
+    "hicr_autotune": (_int, [_vp, _vp, _u64, _u32, _vp, _pu32]),
+    "hicr_tune_add": (_int, [_vp, _vp, _u64, _u32]),
+    "hicr_tune_clear": (_int, [_vp]),
+    "hicr_mlp_set_params": (_int, [_vp, _vp]),
+    "hicr_mlp_get_params": (_int, [_vp, _vp]),
+    "hicr_mlp_forward": (_int, [_vp, _vp, _u32, _vp]),
+    "hicr_mlp_grad": (_int, [_vp, _vp, _vp, _u32, _vp, _vp]),
+    "hicr_mlp_train_step": (_int, [_vp, _vp, _vp, _u32, ctypes.c_float, _vp]),
+    "hicr_last_choice": (_int, [_vp, _pu32]),
+    "hicr_serve": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_serve_cfg),
+                          ctypes.POINTER(hicr_serve_stats)]),
 }
 
 _lib = None
@@ -250,3 +292,99 @@ def hicr_channel_pump(ctx, streams, msg_src_off: np.ndarray, msg_size: np.ndarra
 
 def hicr_channel_abort(ctx) -> int:
     return lib().hicr_channel_abort(ctx)
+
+
+# ------------------------------------------------------ schedule selection
+
+MLP_PARAMS = 7052
+
+
+def _descs(descs):
+    return np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+
+
+def hicr_sched_features(descs: np.ndarray):
+    d = _descs(descs)
+    out = np.zeros(32, dtype=np.float32)
+    rc = lib().hicr_sched_features(d.ctypes.data if d.size else None, d.size, out.ctypes.data)
+    return rc, out
+
+
+def hicr_autotune(ctx, descs: np.ndarray, reps: int = 3):
+    d = _descs(descs)
+    times = np.zeros(NUM_CLASSES, dtype=np.float32)
+    best = _u32(0)
+    rc = lib().hicr_autotune(ctx, d.ctypes.data if d.size else None, d.size, reps,
+                             times.ctypes.data, ctypes.byref(best))
+    return rc, times, best.value
+
+
+def hicr_tune_add(ctx, descs: np.ndarray, cls: int) -> int:
+    d = _descs(descs)
+    return lib().hicr_tune_add(ctx, d.ctypes.data if d.size else None, d.size, cls)
+
+
+def hicr_tune_clear(ctx) -> int:
+    return lib().hicr_tune_clear(ctx)
+
+
+def hicr_mlp_set_params(ctx, params: np.ndarray) -> int:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == MLP_PARAMS
+    return lib().hicr_mlp_set_params(ctx, p.ctypes.data)
+
+
+def hicr_mlp_get_params(ctx):
+    out = np.zeros(MLP_PARAMS, dtype=np.float32)
+    rc = lib().hicr_mlp_get_params(ctx, out.ctypes.data)
+    return rc, out
+
+
+def hicr_mlp_forward(ctx, x_dev: int, batch: int, logits_dev: int) -> int:
+    return lib().hicr_mlp_forward(ctx, x_dev, batch, logits_dev)
+
+
+def hicr_mlp_grad(ctx, x_dev: int, y_dev: int, batch: int, grad_dev: int, loss_dev: int = 0) -> int:
+    return lib().hicr_mlp_grad(ctx, x_dev, y_dev, batch, grad_dev, loss_dev or None)
+
+
+def hicr_mlp_train_step(ctx, x_dev: int, y_dev: int, batch: int, lr: float,
+                        loss_dev: int = 0) -> int:
+    return lib().hicr_mlp_train_step(ctx, x_dev, y_dev, batch, lr, loss_dev or None)
+
+
+def hicr_last_choice(ctx):
+    c = _u32(0)
+    rc = lib().hicr_last_choice(ctx, ctypes.byref(c))
+    return rc, c.value
+
+
+# ------------------------------------------------------------------ serving
+
+def hicr_serve(ctx, reqs: np.ndarray, arena: int, src: int, descs: np.ndarray,
+               msg_src_off: np.ndarray, msg_size: np.ndarray, channels, streams: int = 2,
+               max_batch_reqs: int = 64, sched=None, on_complete=None, admit_ns=None,
+               done_ns=None):
+    """reqs: structured array with the fields of hicr_request (40 bytes each).
+    on_complete(request, arena_off) is called on this thread.  admit_ns /
+    done_ns: optional uint64 numpy arrays of len(reqs), filled in place.
+    Returns (rc, stats)."""
+    assert reqs.dtype.itemsize == ctypes.sizeof(hicr_request)
+    r = np.ascontiguousarray(reqs)
+    d = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+    mo = np.ascontiguousarray(msg_src_off, dtype=np.uint64)
+    ms = np.ascontiguousarray(msg_size, dtype=np.uint64)
+    ch = (ctypes.c_void_p * max(len(channels), 1))(*channels)
+    cb = ON_COMPLETE(lambda user, q, off: on_complete(int(q), int(off))) if on_complete \
+        else ON_COMPLETE()
+    cfg = hicr_serve_cfg(arena, src, streams, max_batch_reqs,
+                         d.ctypes.data if d.size else None, d.size,
+                         mo.ctypes.data if mo.size else None, ms.ctypes.data if ms.size else None,
+                         mo.size, ctypes.cast(ch, ctypes.c_void_p), len(channels), 0,
+                         ctypes.addressof(sched) if sched is not None else None, cb, None,
+                         admit_ns.ctypes.data if admit_ns is not None else None,
+                         done_ns.ctypes.data if done_ns is not None else None)
+    st = hicr_serve_stats()
+    rc = lib().hicr_serve(ctx, r.ctypes.data if r.size else None, r.size, ctypes.byref(cfg),
+                          ctypes.byref(st))
+    return rc, st

@@ -43,3 +43,17 @@ def test_sched_classes_and_strerror():
 def test_ctx_create_rejects_bad_device():
     rc, ctx = H.hicr_ctx_create(10_000, 0)
     assert rc == H.EINVAL and ctx is None
+
+
+def test_features_match_oracle():
+    """The host-side batch feature equals the oracle's definition."""
+    import numpy as np
+    from oracle import mlp
+    from workloads import memcpy as wm
+    for b in range(20):
+        d, _ = wm.family(b)
+        rc, f = H.hicr_sched_features(d)
+        assert rc == H.OK
+        assert np.allclose(f, mlp.features(d["size"]), rtol=1e-6, atol=1e-6)
+    rc, f = H.hicr_sched_features(np.zeros(0, dtype=H.DESC_DTYPE))
+    assert rc == H.OK and not f.any()

@@ -1,0 +1,156 @@
+"""GPU parity of the schedule network against the fp64 oracle.
+
+The GPU kernels compute in fp32, the oracle in fp64; tolerances: logits and
+loss 1e-4 relative, gradients max-abs error <= 1e-4 * max|g| per tensor,
+parameters after Adam steps 2e-5 absolute.  The argmax class must match
+except where the oracle's top two logits are within 1e-5 (relative).
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from workloads import memcpy as wm
+from workloads.mlp_init import he_uniform
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2509_01425_amd import hicr as H
+    rc, ctx = H.hicr_ctx_create(0, 0)
+    assert rc == H.OK
+    yield torch, H, ctx
+    assert H.hicr_ctx_destroy(ctx) == H.OK
+
+
+def _data(seed, B):
+    g = np.random.default_rng(seed)
+    x = np.log2(1 + g.integers(0, 400, size=(B, 32)) * (g.random((B, 32)) < 0.4)).astype(np.float32)
+    y = g.integers(0, 12, size=B).astype(np.int32)
+    return x, y
+
+
+def _tensors(torch, x, y):
+    return (torch.from_numpy(x).cuda().contiguous(), torch.from_numpy(y).cuda().contiguous())
+
+
+@pytest.mark.parametrize("B", [1, 7, 64, 256, 300])
+def test_forward_and_grad_vs_oracle(env, B):
+    torch, H, ctx = env
+    theta = he_uniform(B)
+    assert H.hicr_mlp_set_params(ctx, theta) == H.OK
+    x, y = _data(B, B)
+    xd, yd = _tensors(torch, x, y)
+    logits = torch.zeros(B, 12, dtype=torch.float32, device="cuda")
+    grad = torch.zeros(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    assert H.hicr_mlp_forward(ctx, xd.data_ptr(), B, logits.data_ptr()) == H.OK
+    assert H.hicr_mlp_grad(ctx, xd.data_ptr(), yd.data_ptr(), B, grad.data_ptr(),
+                           loss.data_ptr()) == H.OK
+    th64 = theta.astype(np.float64)
+    z_ref, _ = mlp.forward(th64, x.astype(np.float64))
+    z = logits.cpu().numpy()
+    assert np.allclose(z, z_ref, rtol=1e-4, atol=1e-4 * np.abs(z_ref).max())
+    srt = np.sort(z_ref, axis=1)
+    clear = (srt[:, -1] - srt[:, -2]) > 1e-5 * np.maximum(np.abs(srt[:, -1]), 1e-30)
+    assert (np.argmax(z, 1)[clear] == np.argmax(z_ref, 1)[clear]).all()
+    g_ref = mlp.grad(th64, x.astype(np.float64), y)
+    L_ref = mlp.loss(th64, x.astype(np.float64), y)
+    assert abs(loss.item() - L_ref) <= 1e-4 * max(1.0, abs(L_ref))
+    g = grad.cpu().numpy().astype(np.float64)
+    gp, rp = mlp.unpack(g), mlp.unpack(g_ref)
+    for name, _ in mlp.SHAPES:
+        scale = np.abs(rp[name]).max()
+        assert np.abs(gp[name] - rp[name]).max() <= 1e-4 * max(scale, 1e-12), name
+
+
+def test_adam_steps_track_oracle(env):
+    torch, H, ctx = env
+    theta = he_uniform(9)
+    assert H.hicr_mlp_set_params(ctx, theta) == H.OK
+    opt = mlp.Adam(mlp.N_PARAMS)
+    th = theta.astype(np.float64)
+    for step in range(20):
+        x, y = _data(100 + step, 64)
+        xd, yd = _tensors(torch, x, y)
+        assert H.hicr_mlp_train_step(ctx, xd.data_ptr(), yd.data_ptr(), 64, 1e-3) == H.OK
+        th = opt.step(th, mlp.grad(th, x.astype(np.float64), y))
+    assert H.hicr_fence(ctx) == H.OK
+    rc, got = H.hicr_mlp_get_params(ctx)
+    assert rc == H.OK
+    # Adam normalises each step to about lr per coordinate; fp32 rounding of
+    # tiny gradients can flip a step's size, so allow a few ulp-scale drifts
+    err = np.abs(got.astype(np.float64) - th)
+    assert np.percentile(err, 99) < 2e-5 and err.max() < 2e-3
+
+
+def test_training_reduces_loss(env):
+    torch, H, ctx = env
+    g = np.random.default_rng(3)
+    # a learnable rule: the class is the index of the largest of the first 12 features
+    x = (g.random((2048, 32)) * 4).astype(np.float32)
+    y = np.argmax(x[:, :12], axis=1).astype(np.int32)
+    xd, yd = _tensors(torch, x, y)
+    assert H.hicr_mlp_set_params(ctx, he_uniform(11)) == H.OK
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    assert H.hicr_mlp_grad(ctx, xd.data_ptr(), yd.data_ptr(), 2048,
+                           torch.zeros(mlp.N_PARAMS, device="cuda").data_ptr(),
+                           loss.data_ptr()) == H.OK
+    l0 = loss.item()
+    for ep in range(15):
+        perm = torch.from_numpy(g.permutation(2048)).cuda()
+        for i in range(0, 2048, 256):
+            idx = perm[i:i + 256]
+            xb, yb = xd[idx].contiguous(), yd[idx].contiguous()
+            assert H.hicr_mlp_train_step(ctx, xb.data_ptr(), yb.data_ptr(), 256, 3e-3) == H.OK
+    assert H.hicr_fence(ctx) == H.OK
+    assert H.hicr_mlp_grad(ctx, xd.data_ptr(), yd.data_ptr(), 2048,
+                           torch.zeros(mlp.N_PARAMS, device="cuda").data_ptr(),
+                           loss.data_ptr()) == H.OK
+    assert loss.item() < 0.5 * l0
+
+
+def test_learned_submission_picks_oracle_class_and_moves_bytes(env):
+    """HICR_SCHED_LEARNED: the class chosen on the device equals the oracle
+    network's argmax on the oracle's feature, and the bytes are exact."""
+    torch, H, ctx = env
+    import oracle
+    from workloads import device as wd
+    from workloads.content import content
+    bases, sizes, pool_len, descs, _ = wm.tiny(3)
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    seed = 66
+    wd.fill(pool.data_ptr(), pool_len, seed)
+    torch.cuda.synchronize()
+    slots = np.array([H.hicr_slot_register(ctx, pool.data_ptr() + int(b), int(s))[1]
+                      for b, s in zip(bases, sizes)], dtype=np.uint32)
+    d = descs.copy()
+    d["dst_slot"], d["src_slot"] = slots[descs["dst_slot"]], slots[descs["src_slot"]]
+    for k in range(6):
+        theta = he_uniform(200 + k)
+        # bias the last layer so that several different classes win
+        p = mlp.unpack(theta.astype(np.float64))
+        p["b3"][:] = 0
+        p["b3"][(3 * k) % 12] = 5.0
+        theta = mlp.pack(p).astype(np.float32)
+        assert H.hicr_mlp_set_params(ctx, theta) == H.OK
+        wd.fill(pool.data_ptr(), pool_len, seed)
+        torch.cuda.synchronize()
+        rc, _ = H.hicr_memcpy_batch(ctx, d, H.make_sched(65536, 1, 2, H.SCHED_LEARNED))
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        assert H.hicr_fence(ctx) == H.OK
+        rc, cls = H.hicr_last_choice(ctx)
+        f = mlp.features(descs["size"])
+        assert rc == H.OK and cls == int(mlp.predict(theta.astype(np.float64), f)[0])
+        host = content(seed, 0, pool_len)
+        oc = oracle.Ctx()
+        for b, s in zip(bases, sizes):
+            oc.register(host, offset=int(b), size=int(s))
+        assert oc.memcpy_batch(descs)[0] == oracle.OK
+        assert np.array_equal(pool.cpu().numpy(), host)
+    for s in slots:
+        assert H.hicr_slot_deregister(ctx, int(s)) == H.OK
+
+
