@@ -365,6 +365,31 @@ def bench_serving(torch, H, duration_s=60.0, rate=2000.0, budget=200_000_000_000
     return out
 
 
+def bench_pingpong(torch, H, max_log2=31, reps=10):
+    """Ping-pong goodput G(s) = s / one-way time (half the round trip) for
+    s = 1 B .. 2^max_log2 B, `reps` round trips each (mean and std)."""
+    smax = 1 << max_log2
+    rc, ctx = H.hicr_ctx_create(0, 0)
+    assert rc == H.OK
+    bufs = [torch.empty(smax, dtype=torch.uint8, device="cuda") for _ in range(5)]
+    torch.cuda.synchronize()
+    slots = [H.hicr_slot_register(ctx, b.data_ptr(), smax)[1] for b in bufs]
+    sizes = [1 << k for k in range(max_log2 + 1)]
+    rc, rtt = H.hicr_pingpong(ctx, *slots, sizes, reps + 1, 0)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    rows = []
+    for s, r in zip(sizes, rtt):
+        oneway_s = r[1:].astype(np.float64) / 2 / 1e8   # first round trip is warm-up
+        g = s / oneway_s
+        rows.append({"bytes": s, "goodput_GBps": round(float(g.mean()) / 1e9, 4),
+                     "std_GBps": round(float(g.std()) / 1e9, 4),
+                     "one_way_us": round(float(oneway_s.mean()) * 1e6, 3)})
+    H.hicr_ctx_destroy(ctx)
+    del bufs
+    torch.cuda.empty_cache()
+    return rows
+
+
 def parse_sched(H, text):
     if text in ("tuned", "learned"):
         return H.make_sched(64 << 10, 1, 2, H.SCHED_TUNED if text == "tuned" else H.SCHED_LEARNED)
@@ -383,7 +408,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-channels", action="store_true")
     ap.add_argument("--workload", default="batched",
-                    choices=["batched", "channels", "learned", "serving"])
+                    choices=["batched", "channels", "learned", "serving", "pingpong"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-budget", type=float, default=200e9)
     ap.add_argument("--learned-train", type=int, default=20000)
@@ -407,6 +432,9 @@ def main():
         res = bench_learned(torch, H, n_train=args.learned_train, n_test=args.learned_test,
                             save=args.learned_save)
         print(json.dumps({"learned": res}), flush=True)
+        return
+    if args.workload == "pingpong":
+        print(json.dumps({"pingpong": bench_pingpong(torch, H)}), flush=True)
         return
     if args.workload == "serving":
         res = bench_serving(torch, H, duration_s=args.serve_seconds, budget=int(args.serve_budget))

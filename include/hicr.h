@@ -300,6 +300,20 @@ int hicr_channel_pump(hicr_ctx ctx, const hicr_stream *streams, uint32_t n_strea
 /* Ask running pumps of this context to stop (they end at their next wait). */
 int hicr_channel_abort(hicr_ctx ctx);
 
+/* ---------------------------------------------------- ping-pong (growth) */
+/* Sec. 5, Test Case 1 on one GPU: a pinger and a ponger, each a group of W
+ * workgroups, joined by two opposing channels of one-message capacity (rings
+ * ring_a and ring_b).  For every size, `reps` round trips: the pinger pushes
+ * sizes[i] bytes of `src` into A and waits for the echo in B, which it reads
+ * into `dst`; the ponger takes each message from A into `buf`, frees A, and
+ * pushes `buf` into B.  rtt_ticks[i * reps + k] receives round trip k of size
+ * i in 100 MHz device-clock ticks.  All five slots: HBM, 16-byte aligned, at
+ * least max(sizes) bytes.  wgs_per_endpoint 0 picks max(1, min(256,
+ * size / 1 MiB)).  Synchronous. */
+int hicr_pingpong(hicr_ctx ctx, hicr_slot src, hicr_slot dst, hicr_slot ring_a, hicr_slot ring_b,
+                  hicr_slot buf, const uint64_t *sizes, uint32_t n_sizes, uint32_t reps,
+                  uint32_t wgs_per_endpoint, uint64_t *rtt_ticks);
+
 /* ------------------------------------------------------ serving (growth) */
 /* A continuous-batching server on one context.  Requests arrive over time
  * (arrival_ns from the start of the run, non-decreasing); each is a memcpy

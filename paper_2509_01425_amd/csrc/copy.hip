@@ -28,7 +28,11 @@ typedef v4u v4u_any __attribute__((aligned(1)));  // 16 bytes at any alignment
 
 __device__ __forceinline__ v4u load16(uint64_t a) { return *(const GLOBAL v4u_any *)a; }
 
-__device__ __forceinline__ void store16(uint64_t a, v4u v) { *(GLOBAL v4u *)a = v; }
+// Body stores are non-temporal: the destination is not read again by this
+// kernel, and streaming it past the caches measured ~2% faster on gfx950.
+__device__ __forceinline__ void store16(uint64_t a, v4u v) {
+  __builtin_nontemporal_store(v, (GLOBAL v4u *)a);
+}
 
 __device__ __forceinline__ void copy_byte(uint64_t d, uint64_t s) {
   *(GLOBAL unsigned char *)d = *(const GLOBAL unsigned char *)s;

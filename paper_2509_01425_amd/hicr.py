@@ -140,6 +140,7 @@ _SIGNATURES = {
     "hicr_mlp_grad": (_int, [_vp, _vp, _vp, _u32, _vp, _vp]),
     "hicr_mlp_train_step": (_int, [_vp, _vp, _vp, _u32, ctypes.c_float, _vp]),
     "hicr_last_choice": (_int, [_vp, _pu32]),
+    "hicr_pingpong": (_int, [_vp, _u32, _u32, _u32, _u32, _u32, _vp, _u32, _u32, _u32, _vp]),
     "hicr_serve": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_serve_cfg),
                           ctypes.POINTER(hicr_serve_stats)]),
 }
@@ -388,3 +389,12 @@ def hicr_serve(ctx, reqs: np.ndarray, arena: int, src: int, descs: np.ndarray,
     rc = lib().hicr_serve(ctx, r.ctypes.data if r.size else None, r.size, ctypes.byref(cfg),
                           ctypes.byref(st))
     return rc, st
+
+
+def hicr_pingpong(ctx, src: int, dst: int, ring_a: int, ring_b: int, buf: int, sizes, reps: int,
+                  wgs_per_endpoint: int = 0):
+    sz = np.ascontiguousarray(sizes, dtype=np.uint64)
+    out = np.zeros(sz.size * reps, dtype=np.uint64)
+    rc = lib().hicr_pingpong(ctx, src, dst, ring_a, ring_b, buf, sz.ctypes.data, sz.size, reps,
+                             wgs_per_endpoint, out.ctypes.data)
+    return rc, out.reshape(sz.size, reps)
