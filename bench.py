@@ -407,6 +407,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-channels", action="store_true")
+    ap.add_argument("--copy-grid", type=int, default=0,
+                    help="copy workgroups per CU (0: all that fit)")
     ap.add_argument("--workload", default="batched",
                     choices=["batched", "channels", "learned", "serving", "pingpong"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -449,6 +451,7 @@ def main():
     stream = torch.cuda.Stream()
     rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
     assert rc == H.OK, H.hicr_strerror(rc)
+    assert H.hicr_ctx_set_copy_grid(ctx, args.copy_grid) == H.OK
     pool = torch.empty(wm.B_POOL, dtype=torch.uint8, device="cuda")
     wd.fill(pool.data_ptr(), wm.B_POOL, 7, 0, stream.cuda_stream)
     bases, sizes = wm.batched_slots()
@@ -507,7 +510,8 @@ def main():
                                "slot windows (72 MiB at 8 MiB stride) over a 64 GiB + 64 MiB "
                                "pool, one fused launch + fence per batch",
                    "requests_per_batch": 4096, "slots": 8192, "pool_bytes": wm.B_POOL,
-                   "schedule": args.sched, "gb_per_batch_rw": round(float(np.mean(moved)) / 1e9, 3)},
+                   "schedule": args.sched, "copy_wgs_per_cu": args.copy_grid or "all that fit",
+                   "gb_per_batch_rw": round(float(np.mean(moved)) / 1e9, 3)},
         "p50_ms": round(float(np.percentile(step_s, 50)) * 1e3, 4),
         "p99_ms": round(float(np.percentile(step_s, 99)) * 1e3, 4),
         "roofline": roof,

@@ -108,6 +108,10 @@ const char *hicr_strerror(int code);
 int hicr_last_error(hicr_ctx ctx, char *buf, size_t n);
 /* Default schedule used when hicr_memcpy_batch gets s_or_null == NULL. */
 int hicr_ctx_set_sched(hicr_ctx ctx, const hicr_sched *s);
+/* Copy workgroups launched per compute unit (the persistent grid is at most
+ * CUs x this, capped by what fits); 0 (the default) launches all that fit.
+ * Never changes a byte.  wgs_per_cu > 64 -> HICR_EINVAL. */
+int hicr_ctx_set_copy_grid(hicr_ctx ctx, uint32_t wgs_per_cu);
 
 /* ----------------------------------------------------------------- slots */
 /* Sec. 3.1.3: register the existing allocation [ptr, ptr+size) of memory

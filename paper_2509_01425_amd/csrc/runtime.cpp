@@ -185,7 +185,8 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, 
   // piece count with the smallest chunk of any class.
   const uint32_t bound_chunk = sched_dev ? kChunks[0] : sched.chunk_bytes;
   const uint32_t bound_wgs = sched_dev ? 64u : sched.wgs_per_desc;
-  const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)c->occ;
+  const int per_cu = c->grid_per_cu > 0 ? std::min(c->grid_per_cu, c->occ) : c->occ;
+  const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)per_cu;
   uint64_t i0 = 0;
   while (i0 < n) {
     uint64_t i1 = i0, pieces = 0;
@@ -335,6 +336,13 @@ int hicr_ctx_set_sched(hicr_ctx c, const hicr_sched *s) {
   int rc = check_sched(c, *s);
   if (rc == HICR_OK) c->def_sched = *s;
   return rc;
+}
+
+int hicr_ctx_set_copy_grid(hicr_ctx c, uint32_t wgs_per_cu) {
+  if (!c || wgs_per_cu > 64) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  c->grid_per_cu = (int)wgs_per_cu;
+  return HICR_OK;
 }
 
 int hicr_slot_register(hicr_ctx c, void *ptr, uint64_t size, uint32_t memspace, hicr_slot *out) {

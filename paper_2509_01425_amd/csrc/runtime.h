@@ -64,7 +64,8 @@ struct hicr_ctx_s {
   bool own_stream = false;
   hipStream_t aux = nullptr;  // counter reads, never waits on `stream`
   int n_cu = 1;
-  int occ = 1;  // copy workgroups per CU
+  int occ = 1;       // copy workgroups per CU that fit
+  int grid_per_cu = 0;  // copy workgroups per CU launched (0: all that fit)
   std::vector<hicr::Slot> slots;
   uint64_t *d_counters = nullptr;  // [slot] = {sent, recv}
   uint32_t counter_cap = 0;

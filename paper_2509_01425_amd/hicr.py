@@ -114,6 +114,7 @@ _SIGNATURES = {
     "hicr_strerror": (ctypes.c_char_p, [_int]),
     "hicr_last_error": (_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "hicr_ctx_set_sched": (_int, [_vp, ctypes.POINTER(hicr_sched)]),
+    "hicr_ctx_set_copy_grid": (_int, [_vp, _u32]),
     "hicr_slot_register": (_int, [_vp, _vp, _u64, _u32, _pu32]),
     "hicr_slot_deregister": (_int, [_vp, _u32]),
     "hicr_slot_counters": (_int, [_vp, _u32, _pu64, _pu64]),
@@ -200,6 +201,10 @@ def hicr_last_error(ctx) -> str:
 
 def hicr_ctx_set_sched(ctx, sched: hicr_sched) -> int:
     return lib().hicr_ctx_set_sched(ctx, ctypes.byref(sched))
+
+
+def hicr_ctx_set_copy_grid(ctx, wgs_per_cu: int) -> int:
+    return lib().hicr_ctx_set_copy_grid(ctx, wgs_per_cu)
 
 
 def hicr_slot_register(ctx, ptr: int, size: int, memspace: int = MEM_HBM):

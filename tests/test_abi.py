@@ -57,3 +57,11 @@ def test_features_match_oracle():
         assert np.allclose(f, mlp.features(d["size"]), rtol=1e-6, atol=1e-6)
     rc, f = H.hicr_sched_features(np.zeros(0, dtype=H.DESC_DTYPE))
     assert rc == H.OK and not f.any()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
