@@ -232,17 +232,20 @@ def bench_learned(torch, H, n_train=20000, n_test=1000, reps=3, epochs=30, batch
     yd = torch.from_numpy(y[tr]).cuda()
     g = np.random.default_rng(np.random.SeedSequence([0x48694352, 3, 99]))
     t0 = time.time()
-    for ep in range(epochs):
-        perm = torch.from_numpy(g.permutation(n_train)).cuda()
-        for i in range(0, n_train - batch + 1, batch):
-            idx = perm[i:i + batch]
-            xb, yb = xd[idx].contiguous(), yd[idx].contiguous()
-            assert H.hicr_mlp_train_step(ctx, xb.data_ptr(), yb.data_ptr(), batch, lr) == H.OK
-    assert H.hicr_fence(ctx) == H.OK
-    train_s = time.time() - t0
-    logits = torch.zeros(n_test, 12, dtype=torch.float32, device="cuda")
-    xt = torch.from_numpy(X[te]).cuda()
-    assert H.hicr_mlp_forward(ctx, xt.data_ptr(), n_test, logits.data_ptr()) == H.OK
+    # the mini-batch gathers run on the library's stream, so each training
+    # step reads a finished gather and a freed batch is reused only after it
+    with torch.cuda.stream(stream):
+        for ep in range(epochs):
+            perm = torch.from_numpy(g.permutation(n_train)).cuda()
+            for i in range(0, n_train - batch + 1, batch):
+                idx = perm[i:i + batch]
+                xb, yb = xd[idx].contiguous(), yd[idx].contiguous()
+                assert H.hicr_mlp_train_step(ctx, xb.data_ptr(), yb.data_ptr(), batch, lr) == H.OK
+        assert H.hicr_fence(ctx) == H.OK
+        train_s = time.time() - t0
+        logits = torch.zeros(n_test, 12, dtype=torch.float32, device="cuda")
+        xt = torch.from_numpy(X[te]).cuda()
+        assert H.hicr_mlp_forward(ctx, xt.data_ptr(), n_test, logits.data_ptr()) == H.OK
     pred = np.argmax(logits.cpu().numpy(), axis=1)
     fixed = int(np.argmin(T[tr].sum(axis=0)))
     default = 4

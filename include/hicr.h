@@ -183,7 +183,12 @@ int hicr_tune_clear(hicr_ctx ctx);
  * network and hands the argmax class (ties to the lowest) to the copy kernel
  * without a host round trip.  Without a network HICR_SCHED_LEARNED falls back
  * to the tuned table.  x_dev: [batch][32] features, y_dev: [batch] class
- * labels, logits_dev: [batch][12], grad_dev: [7052] (all device memory). */
+ * labels, logits_dev: [batch][12], grad_dev: [7052] (all device memory).
+ * Labels lie in [0, 12); a sample with a label outside that range gets a NaN
+ * loss and contributes no gradient.  The kernels read and write these buffers
+ * on the context stream: the caller orders their producers before the call
+ * (same stream, or a synchronisation) and keeps them alive until the call's
+ * work has completed. */
 int hicr_mlp_set_params(hicr_ctx ctx, const float *params); /* also resets Adam */
 int hicr_mlp_get_params(hicr_ctx ctx, float *params_out);
 int hicr_mlp_forward(hicr_ctx ctx, const float *x_dev, uint32_t batch, float *logits_dev);

@@ -38,12 +38,15 @@ __global__ __launch_bounds__(256) void softmax_xent_kernel(const float *Z, const
   for (int c = 1; c < kMlpOut; c++) m = fmaxf(m, z[c]);
   float sum = 0.f;
   for (int c = 0; c < kMlpOut; c++) sum += expf(z[c] - m);
+  // A label outside [0, kMlpOut) is never used as an index: the sample's loss
+  // is NaN (so a mean over the batch shows it) and it adds no gradient.
   const int yb = y[b];
+  const bool valid = yb >= 0 && yb < kMlpOut;
   for (int c = 0; c < kMlpOut; c++) {
     const float p = expf(z[c] - m) / sum;
-    dZ[b * kMlpOut + c] = (p - (c == yb ? 1.f : 0.f)) / (float)B;
+    dZ[b * kMlpOut + c] = valid ? (p - (c == yb ? 1.f : 0.f)) / (float)B : 0.f;
   }
-  if (loss) loss[b] = (m + logf(sum)) - z[yb];
+  if (loss) loss[b] = valid ? (m + logf(sum)) - z[yb] : __builtin_nanf("");
 }
 
 // dX[b,i] = (sum_o dY[b,o] W[o,i]) * [Xpre[b,i] > 0]

@@ -19,10 +19,18 @@ pytestmark = pytest.mark.gpu
 def env():
     import torch
     from paper_2509_01425_amd import hicr as H
-    rc, ctx = H.hicr_ctx_create(0, 0)
+    # The library runs on torch's current stream here, so that the tensors
+    # torch makes (gathers, fills) are ordered before the library's kernels,
+    # and blocks torch frees are reused only after those kernels ran.
+    prev = torch.cuda.current_stream()
+    s = torch.cuda.Stream()
+    torch.cuda.set_stream(s)
+    rc, ctx = H.hicr_ctx_create(0, s.cuda_stream)
     assert rc == H.OK
     yield torch, H, ctx
     assert H.hicr_ctx_destroy(ctx) == H.OK
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(prev)
 
 
 def _data(seed, B):
@@ -95,8 +103,8 @@ def test_training_reduces_loss(env):
     xd, yd = _tensors(torch, x, y)
     assert H.hicr_mlp_set_params(ctx, he_uniform(11)) == H.OK
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    assert H.hicr_mlp_grad(ctx, xd.data_ptr(), yd.data_ptr(), 2048,
-                           torch.zeros(mlp.N_PARAMS, device="cuda").data_ptr(),
+    grad = torch.zeros(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    assert H.hicr_mlp_grad(ctx, xd.data_ptr(), yd.data_ptr(), 2048, grad.data_ptr(),
                            loss.data_ptr()) == H.OK
     l0 = loss.item()
     for ep in range(15):
@@ -106,10 +114,34 @@ def test_training_reduces_loss(env):
             xb, yb = xd[idx].contiguous(), yd[idx].contiguous()
             assert H.hicr_mlp_train_step(ctx, xb.data_ptr(), yb.data_ptr(), 256, 3e-3) == H.OK
     assert H.hicr_fence(ctx) == H.OK
-    assert H.hicr_mlp_grad(ctx, xd.data_ptr(), yd.data_ptr(), 2048,
-                           torch.zeros(mlp.N_PARAMS, device="cuda").data_ptr(),
+    assert H.hicr_mlp_grad(ctx, xd.data_ptr(), yd.data_ptr(), 2048, grad.data_ptr(),
                            loss.data_ptr()) == H.OK
     assert loss.item() < 0.5 * l0
+
+
+def test_out_of_range_labels_give_nan_loss_and_no_gradient(env):
+    """Labels outside [0, 12) are never used as indices: the mean loss is NaN
+    and the gradient is the valid samples' share of the batch mean."""
+    torch, H, ctx = env
+    B = 40
+    theta = he_uniform(21)
+    assert H.hicr_mlp_set_params(ctx, theta) == H.OK
+    x, y = _data(21, B)
+    bad = np.array([0, 7, 39])
+    y[bad] = [12, -1, 1 << 30]
+    xd, yd = _tensors(torch, x, y)
+    grad = torch.zeros(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    assert H.hicr_mlp_grad(ctx, xd.data_ptr(), yd.data_ptr(), B, grad.data_ptr(),
+                           loss.data_ptr()) == H.OK
+    assert np.isnan(loss.item())
+    ok = np.setdiff1d(np.arange(B), bad)
+    th64 = theta.astype(np.float64)
+    g_ref = mlp.grad(th64, x[ok].astype(np.float64), y[ok]) * (len(ok) / B)
+    g = grad.cpu().numpy().astype(np.float64)
+    gp, rp = mlp.unpack(g), mlp.unpack(g_ref)
+    for name, _ in mlp.SHAPES:
+        assert np.abs(gp[name] - rp[name]).max() <= 1e-4 * max(np.abs(rp[name]).max(), 1e-12), name
 
 
 def test_learned_submission_picks_oracle_class_and_moves_bytes(env):

@@ -140,6 +140,7 @@ def test_serve_rejections(rig):
     torch, H, ctx, ss, chans, _ = rig
     tr = _small_trace(rate=1000, duration=0.01, batch=3)
     arena = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
     _, aslot = H.hicr_slot_register(ctx, arena.data_ptr(), 1 << 20)
     big = tr.reqs.copy()
     big["hbm_bytes"][0] = 2 << 20
