@@ -303,7 +303,10 @@ typedef struct {
  * launch on `stream`: one GPU wave per producer stream, one workgroup per
  * consumer.  Validated on the host (slots, ranges, sizes, one stream per
  * (channel, producer)); HICR_EINVAL if the launch would not fit on the device
- * at once.  Asynchronous; hicr_fence reports a time-out or abort. */
+ * at once.  Asynchronous; hicr_fence reports a time-out or abort.  A channel
+ * has one producer and one consumer per ring: two pump launches that drive
+ * the same channel must not overlap (same stream, or ordered by the caller),
+ * or the ring's protocol breaks and the pump ends with HICR_ETIMEDOUT. */
 int hicr_channel_pump(hicr_ctx ctx, const hicr_stream *streams, uint32_t n_streams,
                       const hicr_pump_io *io, void *stream);
 /* Ask running pumps of this context to stop (they end at their next wait). */
@@ -330,9 +333,10 @@ int hicr_pingpong(hicr_ctx ctx, hicr_slot src, hicr_slot dst, hicr_slot ring_a, 
  * is the serving budget) for its destinations.  In arrival order, a request
  * is admitted as soon as its destinations fit in the arena; every request
  * admitted since the last launch is fused into one copy launch (memcpy
- * batches, with the given schedule) and one pump launch (bursts; at most one
- * burst per channel per launch); up to `streams` launches are in flight so
- * new work overlaps work already running.  When a launch completes, each of
+ * batches, with the given schedule) and one pump launch (bursts; a burst
+ * waits, and with it every later request, while a launch in flight still
+ * drives its channel); up to `streams` launches are in flight so new work
+ * overlaps work already running.  When a launch completes, each of
  * its requests is timestamped and passed to on_complete while its results
  * are still in the arena; then its arena space is freed.  on_complete runs on
  * the calling thread and must not call into the library on this context.

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <deque>
 #include <map>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -70,6 +71,7 @@ struct Launch {
   bool pump = false;
   Extra x;
   std::vector<uint64_t> reqs;
+  std::vector<hicr_channel> chans;  // channels a pump launch drives
 };
 
 }  // namespace
@@ -142,6 +144,9 @@ int hicr_serve(hicr_ctx c, const hicr_request *rq, uint64_t n, const hicr_serve_
   std::vector<uint64_t> alloc_off(n, 0);
   std::deque<uint64_t> waiting;
   std::vector<Launch> inflight;
+  // A channel's ring has one producer and one consumer: a burst waits while
+  // a pump launch still in flight drives its channel.
+  std::set<hicr_channel> busy;
   uint64_t next = 0, done = 0, n_copy = 0, n_pump = 0, max_reqs = 0;
   const auto t0 = std::chrono::steady_clock::now();
   auto now_ns = [&]() {
@@ -172,6 +177,7 @@ int hicr_serve(hicr_ctx c, const hicr_request *rq, uint64_t n, const hicr_serve_
       if (L.pump) {
         int r = pump_finish(c, L.x);
         if (r != HICR_OK) rc = r;
+        for (hicr_channel ch : L.chans) busy.erase(ch);
       } else {
         (void)hipEventDestroy(L.ev);
       }
@@ -197,8 +203,9 @@ int hicr_serve(hicr_ctx c, const hicr_request *rq, uint64_t n, const hicr_serve_
         const uint64_t r = waiting.front();
         const hicr_request &q = rq[r];
         if (q.kind == HICR_REQ_BURST &&
-            std::find(used.begin(), used.end(), cfg->channels[q.channel]) != used.end())
-          break;  // one burst per channel and launch; the next launch takes it
+            (busy.count(cfg->channels[q.channel]) ||
+             std::find(used.begin(), used.end(), cfg->channels[q.channel]) != used.end()))
+          break;  // one burst per channel in flight; a later launch takes it
         uint64_t off;
         if (!arena.alloc(q.hbm_bytes, &off)) break;  // wait until memory frees up
         alloc_off[r] = off;
@@ -259,6 +266,8 @@ int hicr_serve(hicr_ctx c, const hicr_request *rq, uint64_t n, const hicr_serve_
         if (rc != HICR_OK) break;
         L.ev = L.x.ev;
         L.reqs = burst_reqs;
+        L.chans = used;
+        busy.insert(used.begin(), used.end());
         inflight.push_back(L);
         n_pump++;
       }
