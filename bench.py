@@ -160,6 +160,7 @@ def bench_channels(torch, H, mpsc_mode, steps=3, warmup=1, seed=5):
         e1.record(stream)
         assert rc == H.OK, H.hicr_last_error(ctx)
         assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+        e1.synchronize()
         if k >= warmup:
             times.append(e0.elapsed_time(e1))
     t = ts.cpu().numpy().reshape(2, -1).astype(np.int64)
@@ -281,6 +282,7 @@ def bench_learned(torch, H, n_train=20000, n_test=1000, reps=3, epochs=30, batch
                 e1.record(stream)
                 assert rc == H.OK
                 assert H.hicr_fence(ctx) == H.OK
+                e1.synchronize()  # recorded after the launch the fence waited for
                 ms.append(e0.elapsed_time(e1))
             tot += float(np.median(ms))
         return {"gbps": round(float(nbytes[te].sum()) / tot / 1e6, 1), "total_ms": round(tot, 2)}
