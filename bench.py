@@ -17,6 +17,7 @@ on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sched CLASS|tuned|learned]
        python bench.py --calibrate-copy   (plain-copy kernel for counter scaling)
+       python bench.py --workload {channels,learned,serving,pingpong,tiny,halo}
 """
 import argparse
 import hashlib
@@ -181,13 +182,13 @@ def bench_channels(torch, H, mpsc_mode, steps=3, warmup=1, seed=5):
             "latency_p99_us": round(float(np.percentile(lat_us, 99)), 2)}
 
 
-def bench_learned(torch, H, n_train=20000, n_test=1000, reps=3, epochs=30, batch=256, lr=1e-3,
+def bench_learned(torch, H, n_train=20000, n_test=1000, reps=3, epochs=300, batch=256, lr=1e-3,
                   save=None):
     """The learned-schedule configuration.  Every batch of the training law
     (tiny-like or batched-like family, 8..4096 requests) is autotuned over the
     12 classes (median of `reps` timed runs); the network is trained on the
-    GPU by the library's kernels on the first n_train batches (Adam, 30
-    epochs of 256) and judged on the n_test held-out batches by measured
+    GPU by the library's kernels on the first n_train batches (Adam, 300
+    epochs of mini-batches of 256) and judged on the n_test held-out batches by measured
     copy time against the best fixed class of the training set, the untuned
     default class, the tuned table (nearest training batch) and the
     autotuner's per-batch best."""
@@ -403,19 +404,124 @@ def parse_sched(H, text):
     return s
 
 
+def bench_tiny(torch, H, reps=1000, warmup=50):
+    """Submit-to-fence latency of the tiny batch (64 packed slots, 256
+    requests of 1..8 KiB): one hicr_memcpy_batch + hicr_fence per rep, and
+    one replay of a persistent plan of the same batch + hicr_fence per rep."""
+    from workloads import device as wd
+    from workloads import memcpy as wm
+    bases, sizes, pool_len, descs, _ = wm.tiny(0)
+    stream = torch.cuda.Stream()
+    rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
+    assert rc == H.OK
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), pool_len, 11, 0, stream.cuda_stream)
+    torch.cuda.synchronize()
+    slots = np.array([H.hicr_slot_register(ctx, pool.data_ptr() + int(b), int(z))[1]
+                      for b, z in zip(bases, sizes)], dtype=np.uint32)
+    d = descs.copy()
+    d["dst_slot"], d["src_slot"] = slots[descs["dst_slot"]], slots[descs["src_slot"]]
+    moved = 2 * int(descs["size"].sum())
+    sched = H.hicr_sched_class(0)[1]
+
+    def lat(fn):
+        us = []
+        for k in range(warmup + reps):
+            t0 = time.perf_counter()
+            fn()
+            assert H.hicr_fence(ctx) == H.OK
+            if k >= warmup:
+                us.append((time.perf_counter() - t0) * 1e6)
+        us = np.array(us)
+        return {"p50_us": round(float(np.percentile(us, 50)), 2),
+                "p99_us": round(float(np.percentile(us, 99)), 2),
+                "mean_us": round(float(us.mean()), 2),
+                "gbps": round(moved / (us.mean() * 1e-6) / 1e9, 2)}
+
+    def submit():
+        assert H.hicr_memcpy_batch(ctx, d, sched)[0] == H.OK
+
+    out = {"workload": "tiny: 64 packed slots (1..64 KiB), 256 requests of 1..8 KiB, "
+                       "submit + fence per rep", "bytes_rw": moved, "reps": reps,
+           "memcpy_batch": lat(submit)}
+    rc, plan, _ = H.hicr_plan_create(ctx, d, sched)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    out["plan_replay"] = lat(lambda: H.hicr_plan_launch(plan))
+    assert H.hicr_plan_destroy(plan) == H.OK
+    H.hicr_ctx_destroy(ctx)
+    return out
+
+
+def bench_halo(torch, H, N=704, Py=2, Pz=4, iters=200, reps=3):
+    """Jacobi halo exchange, 2 x 4 subdomains of 704^3 8-byte cells with a
+    ghost layer (22.5 GB): 20 faces x 704 rows of 5,632 B = 14,080 requests,
+    79 MB per exchange.  The 12 classes are autotuned on the exchange; then
+    `iters` exchanges run back to back (one fence at the end) as (a) one
+    hicr_memcpy_batch per exchange and (b) one replay of a persistent plan
+    per exchange, and one exchange + fence is timed alone for latency."""
+    from workloads import halo
+    stream = torch.cuda.Stream()
+    rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
+    assert rc == H.OK
+    sb = halo.sub_bytes(N)
+    pool = torch.empty(Py * Pz * sb, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    slots = np.array([H.hicr_slot_register(ctx, pool.data_ptr() + k * sb, sb)[1]
+                      for k in range(Py * Pz)], dtype=np.uint32)
+    d = halo.exchange(N, Py, Pz)
+    d["dst_slot"], d["src_slot"] = slots[d["dst_slot"]], slots[d["src_slot"]]
+    moved = 2 * int(d["size"].sum())
+    rc, times, best = H.hicr_autotune(ctx, d, reps)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    sched = H.hicr_sched_class(int(best))[1]
+
+    def run(step):
+        step()
+        assert H.hicr_fence(ctx) == H.OK
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            step()
+        assert H.hicr_fence(ctx) == H.OK
+        per = (time.perf_counter() - t0) / iters
+        lat = []
+        for _ in range(50):
+            t1 = time.perf_counter()
+            step()
+            assert H.hicr_fence(ctx) == H.OK
+            lat.append((time.perf_counter() - t1) * 1e6)
+        return {"us_per_exchange": round(per * 1e6, 2), "gbps": round(moved / per / 1e9, 1),
+                "latency_p50_us": round(float(np.percentile(lat, 50)), 2),
+                "latency_p99_us": round(float(np.percentile(lat, 99)), 2)}
+
+    out = {"workload": f"Jacobi halo exchange: {Py}x{Pz} subdomains of {N}^3 8-byte cells, "
+                       f"{len(d)} row copies of {N * 8} B per exchange",
+           "requests": len(d), "bytes_rw": moved,
+           "autotune_ms": [round(float(t), 4) for t in times], "best_class": int(best),
+           "memcpy_batch": run(lambda: H.hicr_memcpy_batch(ctx, d, sched))}
+    rc, plan, _ = H.hicr_plan_create(ctx, d, sched)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    out["plan_replay"] = run(lambda: H.hicr_plan_launch(plan))
+    assert H.hicr_plan_destroy(plan) == H.OK
+    H.hicr_ctx_destroy(ctx)
+    del pool
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sched", default="4")
+    ap.add_argument("--sched", default="5")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-channels", action="store_true")
     ap.add_argument("--copy-grid", type=int, default=0,
-                    help="copy workgroups per CU (0: all that fit)")
+                    help="copy workgroups per CU (0: the library's per-class default)")
     ap.add_argument("--workload", default="batched",
-                    choices=["batched", "channels", "learned", "serving", "pingpong"])
+                    choices=["batched", "channels", "learned", "serving", "pingpong", "tiny",
+                             "halo"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-budget", type=float, default=200e9)
     ap.add_argument("--learned-train", type=int, default=20000)
@@ -439,6 +545,12 @@ def main():
         res = bench_learned(torch, H, n_train=args.learned_train, n_test=args.learned_test,
                             save=args.learned_save)
         print(json.dumps({"learned": res}), flush=True)
+        return
+    if args.workload == "halo":
+        print(json.dumps({"halo": bench_halo(torch, H)}), flush=True)
+        return
+    if args.workload == "tiny":
+        print(json.dumps({"tiny": bench_tiny(torch, H)}), flush=True)
         return
     if args.workload == "pingpong":
         print(json.dumps({"pingpong": bench_pingpong(torch, H)}), flush=True)
@@ -515,7 +627,7 @@ def main():
                                "slot windows (72 MiB at 8 MiB stride) over a 64 GiB + 64 MiB "
                                "pool, one fused launch + fence per batch",
                    "requests_per_batch": 4096, "slots": 8192, "pool_bytes": wm.B_POOL,
-                   "schedule": args.sched, "copy_wgs_per_cu": args.copy_grid or "all that fit",
+                   "schedule": args.sched, "copy_wgs_per_cu": args.copy_grid or "library default for the class",
                    "gb_per_batch_rw": round(float(np.mean(moved)) / 1e9, 3)},
         "p50_ms": round(float(np.percentile(step_s, 50)) * 1e3, 4),
         "p99_ms": round(float(np.percentile(step_s, 99)) * 1e3, 4),

@@ -56,10 +56,16 @@ extern "C" {
 #define HICR_EDEVICE (-9)      /* HIP runtime or device-side error               */
 #define HICR_EBUSY (-10)       /* object still has transfers in flight           */
 
-/* Memory spaces (Sec. 3.1.2).  Only HBM -> HBM transfers are supported; a
- * request touching a host slot is rejected with HICR_EUNSUPPORTED. */
+/* Memory spaces (Sec. 3.1.2): the GPU's HBM and pinned host memory.  The
+ * copy kernel reaches both (host memory over the host link), so memcpy
+ * supports every pair by default; hicr_ctx_set_pairs narrows the set, and a
+ * request whose pair is outside it is rejected with HICR_EUNSUPPORTED
+ * (Sec. 3.1.4).  Channels and ping-pong rings are HBM only. */
 #define HICR_MEM_HBM 0u
 #define HICR_MEM_HOST 1u
+/* bit (2 * dst_space + src_space) of a pair mask: that pair is supported */
+#define HICR_PAIR(dst_space, src_space) (1u << (2u * (dst_space) + (src_space)))
+#define HICR_PAIRS_ALL 0xfu
 
 typedef struct hicr_ctx_s *hicr_ctx;
 typedef uint32_t hicr_slot;
@@ -109,15 +115,23 @@ int hicr_last_error(hicr_ctx ctx, char *buf, size_t n);
 /* Default schedule used when hicr_memcpy_batch gets s_or_null == NULL. */
 int hicr_ctx_set_sched(hicr_ctx ctx, const hicr_sched *s);
 /* Copy workgroups launched per compute unit (the persistent grid is at most
- * CUs x this, capped by what fits); 0 (the default) launches all that fit.
- * Never changes a byte.  wgs_per_cu > 64 -> HICR_EINVAL. */
+ * CUs x this, capped by what fits).  0 (the default) picks by schedule: 4 for
+ * 4 KiB chunks, otherwise 1 at unroll 4 and 2 at unroll 2, and 2 when the
+ * network chooses the class on the device.  Never changes a byte.
+ * wgs_per_cu > 64 -> HICR_EINVAL. */
 int hicr_ctx_set_copy_grid(hicr_ctx ctx, uint32_t wgs_per_cu);
+/* Memory-space pairs memcpy accepts from now on (HICR_PAIR bits; default
+ * HICR_PAIRS_ALL).  Requests already accepted are not re-checked.  Bits
+ * outside HICR_PAIRS_ALL -> HICR_EINVAL. */
+int hicr_ctx_set_pairs(hicr_ctx ctx, uint32_t pair_mask);
 
 /* ----------------------------------------------------------------- slots */
 /* Sec. 3.1.3: register the existing allocation [ptr, ptr+size) of memory
  * space `memspace` as a slot.  For HICR_MEM_HBM the range must lie inside one
- * device allocation of this context's device.  size == 0 -> HICR_EINVAL.
- * Slots may alias.  Counters start at zero. */
+ * device allocation of this context's device; for HICR_MEM_HOST it must be
+ * pinned host memory (hipHostMalloc, torch pin_memory) that the device can
+ * address -- pageable or device memory -> HICR_EINVAL.  size == 0 ->
+ * HICR_EINVAL.  Slots may alias.  Counters start at zero. */
 int hicr_slot_register(hicr_ctx ctx, void *ptr, uint64_t size, uint32_t memspace,
                        hicr_slot *out);
 /* Forget a slot.  HICR_EBUSY while any submitted transfer is unfenced. */
@@ -153,6 +167,31 @@ int hicr_fence(hicr_ctx ctx);
  * once when nothing is in flight that could still raise them. */
 int hicr_fence_slot(hicr_ctx ctx, hicr_slot slot, uint64_t exp_sent, uint64_t exp_recv,
                     uint64_t timeout_ns);
+
+/* ------------------------------------------ persistent batch plans (growth) */
+/* Sec. 3.1.4 memcpy batches that repeat unchanged (a halo exchange, a fixed
+ * gather): the batch is validated, resolved to addresses and uploaded once,
+ * and its fused copy launches are captured in a HIP graph; every
+ * hicr_plan_launch replays the graph.  One replay moves every request once
+ * and raises each request's sent/recv counters once, like one
+ * hicr_memcpy_batch of the same requests; hicr_fence (and fence_slot) wait
+ * for replays as for any other transfer.
+ *   d[0..n): requests as for hicr_memcpy_batch (copied; the caller may reuse
+ *   the array at once).  s_or_null: FIXED, TUNED (resolved now) or LEARNED
+ *   (the network runs once on the device now; every replay reads its choice
+ *   from device memory).  On a rejected request: its code, *bad_index set, no
+ *   plan.  n = 0 gives a plan whose launches move nothing.
+ * While a plan exists the slots it names cannot be deregistered (HICR_EBUSY).
+ * Replays of one plan are serialised: a launch on another stream than the
+ * previous one first waits for the previous replay.  Slot contents may change
+ * between replays; slot addresses may not (they are resolved at creation). */
+typedef struct hicr_plan_s *hicr_plan;
+int hicr_plan_create(hicr_ctx ctx, const hicr_desc *d, uint64_t n, const hicr_sched *s_or_null,
+                     hicr_plan *out, uint64_t *bad_index_or_null);
+/* Replay once on `stream` (NULL: the context stream).  Asynchronous. */
+int hicr_plan_launch(hicr_plan plan, void *stream);
+/* Wait for the plan's last replay, then free it and release its slots. */
+int hicr_plan_destroy(hicr_plan plan);
 
 
 
@@ -202,6 +241,34 @@ int hicr_mlp_grad(hicr_ctx ctx, const float *x_dev, const int32_t *y_dev, uint32
  * on the context stream, completed by hicr_fence. */
 int hicr_mlp_train_step(hicr_ctx ctx, const float *x_dev, const int32_t *y_dev, uint32_t batch,
                         float lr, float *loss_dev);
+
+/* --------------------------------------------------- data objects (growth) */
+/* Sec. 4.3 Data Objects: a block [offset, offset+size) of a local slot is
+ * published under an identifier that is unique within the context and never
+ * reused; whoever holds the identifier (it may travel through a channel)
+ * obtains a handle -- the object's metadata -- and starts an asynchronous
+ * get, a memcpy of the whole object into its own slot that completes at the
+ * next fence and counts on both slots like any memcpy.  A published object
+ * keeps its slot from being deregistered (HICR_EBUSY).  Its bytes are read
+ * when the get runs: the publisher keeps them unchanged until the getter's
+ * fence. */
+typedef struct {
+  uint64_t id;
+  uint64_t size;     /* bytes */
+  uint64_t offset;   /* in the publishing slot */
+  hicr_slot slot;    /* publishing slot */
+  uint32_t memspace; /* memory space of the publishing slot */
+} hicr_dobj_handle;
+/* size == 0 or [offset, offset+size) outside the slot -> HICR_ERANGE. */
+int hicr_dobj_publish(hicr_ctx ctx, hicr_slot slot, uint64_t offset, uint64_t size,
+                      uint64_t *id_out);
+/* Unknown or withdrawn id -> HICR_EINVAL. */
+int hicr_dobj_get_handle(hicr_ctx ctx, uint64_t id, hicr_dobj_handle *out);
+/* Queue the copy of the object into dst at dst_off (the rules of
+ * hicr_memcpy).  A handle whose object was withdrawn -> HICR_EINVAL. */
+int hicr_dobj_get(hicr_ctx ctx, const hicr_dobj_handle *h, hicr_slot dst, uint64_t dst_off);
+/* Withdraw an object; gets already queued still run.  Unknown id -> HICR_EINVAL. */
+int hicr_dobj_unpublish(hicr_ctx ctx, uint64_t id);
 
 /* -------------------------------------------------------------- channels */
 /* Sec. 4.3 Channels: circular buffers pre-allocated at the consumer.  The

@@ -96,12 +96,12 @@ namespace hicr {
 int wait_extra(hicr_ctx c) {
   int rc = HICR_OK;
   if (c->push_pending) {
-    hipError_t e = hipEventSynchronize(c->push_ev);
+    hipError_t e = sync_event(c->push_ev);
     c->push_pending = false;
     if (e != hipSuccess) rc = hip_fail(c, e, "waiting for channel pushes");
   }
   for (Extra &x : c->extra) {
-    hipError_t e = hipEventSynchronize(x.ev);
+    hipError_t e = sync_event(x.ev);
     if (e != hipSuccess) rc = hip_fail(c, e, "waiting for a pump");
     int r = pump_finish(c, x);
     if (rc == HICR_OK) rc = r;

@@ -6,17 +6,20 @@
 //      inclusive prefix scan of those counts into LDS (wavefront scans with
 //      __shfl_up, then a cross-wave carry), so the batch becomes one global
 //      index space of pieces;
-//   2. workgroup g takes pieces g, g + G, g + 2G, ...; a 64-ary search over
-//      the LDS table (two ballots for 4,096 requests) finds the request;
-//   3. a piece is copied with 16-byte destination-aligned vector stores and
-//      16-byte loads at whatever alignment the source has (the HSA ABI runs
-//      gfx950 in unaligned-access mode), `unroll` vectors in flight per lane;
-//      the at most 15 bytes before the first and after the last aligned
-//      destination vector are copied byte by byte, so no store ever touches
-//      a byte outside the request;
+//   2. every wavefront is an independent worker: wave w of workgroup g
+//      takes pieces 4g + w, 4g + w + 4G, ...; a 64-ary search over the LDS
+//      table (two ballots for 4,096 requests) finds the request;
+//   3. a piece is copied by its wave with 16-byte destination-aligned vector
+//      stores and 16-byte loads at whatever alignment the source has (the HSA
+//      ABI runs gfx950 in unaligned-access mode), `unroll` vectors in flight
+//      per lane; the at most 15 bytes before the first and after the last
+//      aligned destination vector are copied byte by byte, so no store ever
+//      touches a byte outside the request;
 //   4. the last workgroup to finish (a device-scope counter) raises the
 //      per-slot sent/received transfer counters of every request, after an
-//      acquire that orders it behind every other workgroup's release.
+//      acquire that orders it behind every other workgroup's release; the
+//      counts are summed per slot in LDS first, so a slot named by many
+//      requests costs one device atomic per counter.
 #include "internal.h"
 
 namespace hicr {
@@ -60,54 +63,55 @@ __device__ __forceinline__ uint32_t find_piece_owner(const uint32_t *ends, uint3
   return lo + (uint32_t)__ffsll((unsigned long long)m) - 1;
 }
 
-// Copy nv 16-byte vectors: destination d is 16-byte aligned, source s is not
-// necessarily.  Lane t of the workgroup moves vectors t, t + 256, ... with U
-// loads issued before the matching stores.
+// Copy nv 16-byte vectors with one wavefront: destination d is 16-byte
+// aligned, source s is not necessarily.  Lane t moves vectors t, t + 64, ...
+// with U loads issued before the matching stores.
 template <int U>
-__device__ __forceinline__ void copy_body(uint64_t d, uint64_t s, uint64_t nv, uint32_t tid) {
-  constexpr uint64_t step = (uint64_t)kCopyBlock * U;
+__device__ __forceinline__ void copy_body(uint64_t d, uint64_t s, uint64_t nv, uint32_t lane) {
+  constexpr uint64_t step = 64ull * U;
   const uint64_t full = nv - nv % step;
   uint64_t base = 0;
   for (; base < full; base += step) {
     v4u r[U];
 #pragma unroll
-    for (int k = 0; k < U; k++) r[k] = load16(s + (base + tid + (uint64_t)k * kCopyBlock) * 16);
+    for (int k = 0; k < U; k++) r[k] = load16(s + (base + lane + 64ull * k) * 16);
 #pragma unroll
-    for (int k = 0; k < U; k++) store16(d + (base + tid + (uint64_t)k * kCopyBlock) * 16, r[k]);
+    for (int k = 0; k < U; k++) store16(d + (base + lane + 64ull * k) * 16, r[k]);
   }
   v4u r[U];
 #pragma unroll
   for (int k = 0; k < U; k++) {
-    uint64_t idx = base + tid + (uint64_t)k * kCopyBlock;
+    uint64_t idx = base + lane + 64ull * k;
     if (idx < nv) r[k] = load16(s + idx * 16);
   }
 #pragma unroll
   for (int k = 0; k < U; k++) {
-    uint64_t idx = base + tid + (uint64_t)k * kCopyBlock;
+    uint64_t idx = base + lane + 64ull * k;
     if (idx < nv) store16(d + idx * 16, r[k]);
   }
 }
 
 // Copy destination bytes [lo, hi) from source address s (the source byte of
-// lo).  The head [lo, a0) and tail [a1, hi) are each shorter than 16 bytes.
+// lo) with one wavefront.  The head [lo, a0) and tail [a1, hi) are each
+// shorter than 16 bytes: lanes 0..14 take the head, lanes 32..46 the tail.
 __device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s, uint32_t unroll,
-                                           uint32_t tid) {
+                                           uint32_t lane) {
   uint64_t a0 = (lo + 15) & ~(uint64_t)15;
   if (a0 > hi) a0 = hi;
   uint64_t a1 = hi & ~(uint64_t)15;
   if (a1 < a0) a1 = a0;
-  if (tid < a0 - lo) copy_byte(lo + tid, s + tid);
-  if (tid >= 64 && tid - 64 < hi - a1) {
-    uint64_t o = (a1 - lo) + (tid - 64);
+  if (lane < a0 - lo) copy_byte(lo + lane, s + lane);
+  if (lane >= 32 && lane - 32 < hi - a1) {
+    uint64_t o = (a1 - lo) + (lane - 32);
     copy_byte(lo + o, s + o);
   }
   const uint64_t nv = (a1 - a0) >> 4;
   if (nv == 0) return;
   const uint64_t d16 = a0, s16 = s + (a0 - lo);
   if (unroll >= 4)
-    copy_body<4>(d16, s16, nv, tid);
+    copy_body<4>(d16, s16, nv, lane);
   else
-    copy_body<2>(d16, s16, nv, tid);
+    copy_body<2>(d16, s16, nv, lane);
 }
 
 __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s0,
@@ -146,8 +150,11 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
   __syncthreads();
   const uint32_t total = n ? ends[n - 1] : 0;
 
-  // 2-3. persistent loop over pieces
-  for (uint32_t q = blockIdx.x; q < total; q += gridDim.x) {
+  // 2-3. persistent loop over pieces, one wavefront per piece
+  constexpr uint32_t kWaves = kCopyBlock / 64;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
+  const uint32_t stride = gridDim.x * kWaves;
+  for (uint32_t q = first; q < total; q += stride) {
     uint32_t i = __builtin_amdgcn_readfirstlane(find_piece_owner(ends, n, q, lane));
     uint32_t j = q - (i ? ends[i - 1] : 0u);
     const uint64_t dst = b.dst[i], src = b.src[i], size = b.size[i];
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
     uint64_t lo = base + (uint64_t)j * L, hi = lo + L;
     if (lo < dst) lo = dst;
     if (hi > dst + size) hi = dst + size;
-    if (lo < hi) copy_range(lo, hi, src + (lo - dst), s.unroll, tid);
+    if (lo < hi) copy_range(lo, hi, src + (lo - dst), s.unroll, lane);
   }
 
   // 4. completion: release this workgroup's stores, count finished groups
@@ -170,13 +177,47 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
   __syncthreads();
   if (is_last && counters) {
     __threadfence();
+    // Requests often share slots (a halo exchange names 8 slots 14,080 times),
+    // and device atomics on one address serialise.  The counts are therefore
+    // summed per slot in an LDS table first -- ends[] is free now -- so each
+    // slot costs one device atomic per counter.  A bucket holds one slot and
+    // a packed count (sent in bits 0..15, received in 16..31: a launch has at
+    // most 4,096 requests); a slot whose bucket another slot holds goes
+    // straight to device memory.  Slot ids are below 2^20, never ~0u.
+    constexpr uint32_t kBuckets = kMaxLdsDescs / 2;
+    constexpr uint32_t kEmpty = 0xffffffffu;
+    static_assert(kMaxLdsDescs <= 0xffff, "per-launch counts must fit 16 bits");
+    uint32_t *key = ends, *cnt = ends + kBuckets;
+    for (uint32_t h = tid; h < kBuckets; h += kCopyBlock) {
+      key[h] = kEmpty;
+      cnt[h] = 0;
+    }
+    __syncthreads();
+    auto add = [&](uint32_t slot, uint32_t inc, uint64_t *direct) {
+      const uint32_t h = slot & (kBuckets - 1);
+      const uint32_t old = atomicCAS(&key[h], kEmpty, slot);
+      if (old == kEmpty || old == slot)
+        atomicAdd(&cnt[h], inc);
+      else
+        __hip_atomic_fetch_add(direct, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
     for (uint32_t i = tid; i < n; i += kCopyBlock) {
       const uint64_t sp = b.slots[i];
-      const uint64_t dslot = sp & 0xffffffffull, sslot = sp >> 32;
-      __hip_atomic_fetch_add(&counters[2 * sslot], 1ull, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&counters[2 * dslot + 1], 1ull, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t dslot = (uint32_t)(sp & 0xffffffffull), sslot = (uint32_t)(sp >> 32);
+      add(sslot, 1u, &counters[2 * (uint64_t)sslot]);
+      add(dslot, 1u << 16, &counters[2 * (uint64_t)dslot + 1]);
+    }
+    __syncthreads();
+    for (uint32_t h = tid; h < kBuckets; h += kCopyBlock) {
+      const uint32_t k = key[h];
+      if (k == kEmpty) continue;
+      const uint32_t c = cnt[h];
+      if (c & 0xffffu)
+        __hip_atomic_fetch_add(&counters[2 * (uint64_t)k], (uint64_t)(c & 0xffffu),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c >> 16)
+        __hip_atomic_fetch_add(&counters[2 * (uint64_t)k + 1], (uint64_t)(c >> 16),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (is_last && tid == 0)

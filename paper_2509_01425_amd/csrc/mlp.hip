@@ -117,14 +117,21 @@ __global__ __launch_bounds__(256) void sched_infer_kernel(const uint64_t *sizes,
                                                           DevSched *out) {
   __shared__ uint32_t hist[kMlpIn];
   __shared__ float x[kMlpIn], h1[kMlpHidden], h2[kMlpHidden], z[kMlpOut];
+  // The parameters (28 KiB) are staged in LDS with coalesced 16-byte loads:
+  // after a large copy they are no longer in the caches, and the dot products
+  // below would otherwise wait on one uncoalesced load chain per layer.
+  __shared__ float4 P4[kMlpParams / 4];
+  static_assert(kMlpParams % 4 == 0, "parameter block is a whole number of float4");
   const int t = threadIdx.x;
+  for (int i = t; i < kMlpParams / 4; i += 256) P4[i] = reinterpret_cast<const float4 *>(params)[i];
   if (t < kMlpIn) hist[t] = 0;
   __syncthreads();
   for (uint32_t i = t; i < n; i += 256) atomicAdd(&hist[size_bin(sizes[i])], 1u);
   __syncthreads();
   if (t < kMlpIn) x[t] = log2f(1.f + (float)hist[t]);
   __syncthreads();
-  const float *W1 = params, *b1 = W1 + kMlpHidden * kMlpIn, *W2 = b1 + kMlpHidden,
+  const float *P = reinterpret_cast<const float *>(P4);
+  const float *W1 = P, *b1 = W1 + kMlpHidden * kMlpIn, *W2 = b1 + kMlpHidden,
               *b2 = W2 + kMlpHidden * kMlpHidden, *W3 = b2 + kMlpHidden,
               *b3 = W3 + kMlpOut * kMlpHidden;
   if (t < kMlpHidden) {

@@ -1,0 +1,209 @@
+// plan.cpp -- persistent memcpy batches replayed from a HIP graph.
+//
+// A plan is a batch of memcpy requests (HiCR Sec. 3.1.4) that a caller
+// repeats unchanged.  Validation, address resolution and the upload happen
+// once; the fused copy launches (one per sub-batch of at most 4,096
+// requests) are captured from a private stream into a graph, and each replay
+// is one hipGraphLaunch.  The graph holds kernel nodes only: the
+// finished-workgroup word that the copy kernel uses is zeroed once here and
+// returned to zero by the last workgroup of every launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace hicr;
+
+struct hicr_plan_s {
+  hicr_ctx c = nullptr;
+  uint64_t n = 0;
+  void *d = nullptr;          // device SoA {dst, src, size, slot pair}, 32 B per request
+  char *words = nullptr;      // grid_done (offset 0), device-chosen schedule (offset 16)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev = nullptr;    // end of the last replay
+  hipStream_t last = nullptr; // stream of the last replay
+  bool launched = false;
+  std::vector<hicr_slot> slots;  // distinct slots the requests name
+};
+
+namespace {
+
+void free_plan(hicr_plan p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->ev) (void)hipEventDestroy(p->ev);
+  if (p->d) (void)hipFree(p->d);
+  if (p->words) (void)hipFree(p->words);
+  for (hicr_slot s : p->slots) p->c->slots[s].plan_refs--;
+  delete p;
+}
+
+int wait_plan(hicr_ctx c, hicr_plan p) {
+  if (!p->launched) return HICR_OK;
+  hipError_t e = sync_event(p->ev);
+  p->launched = false;
+  return e == hipSuccess ? HICR_OK : hip_fail(c, e, "waiting for a plan replay");
+}
+
+}  // namespace
+
+namespace hicr {
+
+int wait_plans(hicr_ctx c) {
+  int rc = HICR_OK;
+  for (hicr_plan p : c->plans) {
+    int r = wait_plan(c, p);
+    if (r != HICR_OK) rc = r;
+  }
+  return rc;
+}
+
+bool plans_inflight(hicr_ctx c) {
+  for (hicr_plan p : c->plans) {
+    if (!p->launched) continue;
+    if (hipEventQuery(p->ev) == hipSuccess)
+      p->launched = false;
+    else
+      return true;
+  }
+  return false;
+}
+
+void destroy_plans(hicr_ctx c) {
+  for (hicr_plan p : c->plans) {
+    (void)wait_plan(c, p);
+    free_plan(p);
+  }
+  c->plans.clear();
+}
+
+}  // namespace hicr
+
+extern "C" {
+
+int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched *s,
+                     hicr_plan *out, uint64_t *bad) {
+  if (!c || !out || (n && !d)) return HICR_EINVAL;
+  *out = nullptr;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  for (uint64_t i = 0; i < n; i++) {
+    int rc = check_desc(c, d[i]);
+    if (rc != HICR_OK) {
+      if (bad) *bad = i;
+      return fail(c, rc, "plan request %llu rejected", (unsigned long long)i);
+    }
+  }
+  hicr_sched sched = s ? *s : c->def_sched;
+  bool learned = false;
+  if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
+    int rc = choose_sched(c, d, n, sched.mode, &sched, &learned);
+    if (rc != HICR_OK) return rc;
+  } else if (sched.mode != HICR_SCHED_FIXED) {
+    return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
+  }
+  int rc = check_sched(c, sched);
+  if (rc != HICR_OK) return rc;
+
+  hicr_plan p = new (std::nothrow) hicr_plan_s();
+  if (!p) return HICR_ENOMEM;
+  p->c = c;
+  p->n = n;
+  std::vector<hicr_slot> sl;
+  sl.reserve(2 * n);
+  for (uint64_t i = 0; i < n; i++) {
+    sl.push_back(d[i].dst_slot);
+    sl.push_back(d[i].src_slot);
+  }
+  std::sort(sl.begin(), sl.end());
+  sl.erase(std::unique(sl.begin(), sl.end()), sl.end());
+  for (hicr_slot x : sl) c->slots[x].plan_refs++;
+  p->slots = sl;
+
+  std::vector<uint64_t> h(4 * std::max<uint64_t>(n, 1));
+  pack_batch(c, d, n, h.data());
+  hipStream_t cs = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&p->ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&p->words, 64);
+  if (e == hipSuccess) e = hipMemset(p->words, 0, 64);
+  if (e == hipSuccess && n) e = hipMalloc(&p->d, n * 32);
+  if (e == hipSuccess && n) e = hipMemcpy(p->d, h.data(), n * 32, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    if (cs) (void)hipStreamDestroy(cs);
+    free_plan(p);
+    return hip_fail(c, e, "allocating a plan");
+  }
+  const uint64_t *dd = static_cast<const uint64_t *>(p->d);
+  DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
+  const DevSched *sched_dev = nullptr;
+  if (learned && n) {
+    // the network chooses once, from the uploaded sizes; replays read the choice
+    DevSched *choice = reinterpret_cast<DevSched *>(p->words + 16);
+    e = sched_infer(c, dd + 2 * n, n, choice, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      free_plan(p);
+      return hip_fail(c, e, "schedule inference for a plan");
+    }
+    sched_dev = choice;
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    uint32_t *grid_done = reinterpret_cast<uint32_t *>(p->words);
+    rc = launch_batch(c, dd, n, h.data(), h.data() + 2 * n, ds, sched_dev, c->d_counters,
+                      grid_done, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    p->graph = graph;
+    if (rc == HICR_OK && e2 != hipSuccess) rc = hip_fail(c, e2, "capturing a plan");
+    if (rc == HICR_OK) {
+      e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) rc = hip_fail(c, e, "instantiating a plan");
+    }
+  } else {
+    rc = hip_fail(c, e, "capturing a plan");
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc != HICR_OK) {
+    free_plan(p);
+    return rc;
+  }
+  c->plans.push_back(p);
+  *out = p;
+  return HICR_OK;
+}
+
+int hicr_plan_launch(hicr_plan p, void *stream) {
+  if (!p) return HICR_EINVAL;
+  hicr_ctx c = p->c;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  hipError_t e = hipSuccess;
+  if (p->launched && s != p->last) e = hipStreamWaitEvent(s, p->ev, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(p->exec, s);
+  if (e == hipSuccess) e = hipEventRecord(p->ev, s);
+  if (e != hipSuccess) return hip_fail(c, e, "launching a plan");
+  p->launched = true;
+  p->last = s;
+  return HICR_OK;
+}
+
+int hicr_plan_destroy(hicr_plan p) {
+  if (!p) return HICR_EINVAL;
+  hicr_ctx c = p->c;
+  std::lock_guard<std::mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  int rc = wait_plan(c, p);
+  c->plans.erase(std::remove(c->plans.begin(), c->plans.end(), p), c->plans.end());
+  free_plan(p);
+  return rc;
+}
+
+}  // extern "C"

@@ -67,7 +67,7 @@ int check_desc(hicr_ctx c, const hicr_desc &d) {
   const Slot &ds = c->slots[d.dst_slot], &ss = c->slots[d.src_slot];
   if (d.dst_off > ds.size || d.size > ds.size - d.dst_off) return HICR_ERANGE;
   if (d.src_off > ss.size || d.size > ss.size - d.src_off) return HICR_ERANGE;
-  if (ds.space != HICR_MEM_HBM || ss.space != HICR_MEM_HBM) return HICR_EUNSUPPORTED;
+  if (!(c->pair_mask & HICR_PAIR(ds.space, ss.space))) return HICR_EUNSUPPORTED;
   return HICR_OK;
 }
 
@@ -82,9 +82,22 @@ bool any_inflight(hicr_ctx c) {
   return false;
 }
 
+hipError_t sync_event(hipEvent_t e) {
+  // A fence usually waits for a few microseconds of GPU work: poll first
+  // (hipEventSynchronize may sleep and wake tens of microseconds late), then
+  // block, so a long wait does not burn a core.
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t q = hipEventQuery(e);
+    if (q != hipErrorNotReady) return q;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(200)) break;
+  }
+  return hipEventSynchronize(e);
+}
+
 int wait_sub(hicr_ctx c, Sub &s) {
   if (!s.inflight) return HICR_OK;
-  hipError_t e = hipEventSynchronize(s.ev);
+  hipError_t e = sync_event(s.ev);
   s.inflight = false;
   if (e != hipSuccess) return hip_fail(c, e, "waiting for a batch");
   return HICR_OK;
@@ -97,6 +110,8 @@ int wait_all(hicr_ctx c) {
     if (r != HICR_OK) rc = r;
   }
   int r = wait_extra(c);
+  if (r != HICR_OK) rc = r;
+  r = wait_plans(c);
   if (r != HICR_OK) rc = r;
   return rc;
 }
@@ -117,25 +132,67 @@ static int ensure_capacity(hicr_ctx c, Sub &s, uint64_t n) {
   return HICR_OK;
 }
 
-int ensure_counter_capacity(hicr_ctx c, uint32_t nslots) {
-  if (nslots <= c->counter_cap) return HICR_OK;
-  int rc = wait_all(c);
-  if (rc != HICR_OK) return rc;
-  uint32_t cap = std::max<uint32_t>(nslots, 2 * c->counter_cap);
-  uint64_t *nc = nullptr;
-  hipError_t e = hipMalloc(&nc, (size_t)cap * 16);
-  if (e != hipSuccess) return fail(c, HICR_ENOMEM, "counter table of %u slots", cap);
-  e = hipMemset(nc, 0, (size_t)cap * 16);
-  if (e == hipSuccess && c->counter_cap)
-    e = hipMemcpy(nc, c->d_counters, (size_t)c->counter_cap * 16, hipMemcpyDeviceToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(nc);
-    return hip_fail(c, e, "growing the counter table");
-  }
-  (void)hipFree(c->d_counters);
-  c->d_counters = nc;
-  c->counter_cap = cap;
+// The counter table is allocated once, for kMaxSlots slots (16 MiB), so its
+// address never changes: captured plans keep a valid pointer to it.
+static int alloc_counters(hicr_ctx c) {
+  hipError_t e = hipMalloc(&c->d_counters, (size_t)kMaxSlots * 16);
+  if (e == hipSuccess) e = hipMemset(c->d_counters, 0, (size_t)kMaxSlots * 16);
+  if (e != hipSuccess) return hip_fail(c, e, "allocating the counter table");
+  c->counter_cap = kMaxSlots;
   return HICR_OK;
+}
+
+// Copy workgroups per CU when the caller has not fixed it.  Measured on the
+// batched workload (256 CUs): with 64 KiB or 1 MiB pieces one workgroup per CU
+// (four wavefronts) saturates HBM at unroll 4 and two do at unroll 2; more
+// groups only add contention.  4 KiB pieces spend more time per piece on the
+// search and want four.  A class chosen on the device is not known here: two.
+int default_grid_per_cu(const DevSched &ds, bool device_choice) {
+  if (device_choice) return 2;
+  if (ds.chunk <= (4u << 10)) return 4;
+  return ds.unroll >= 4 ? 1 : 2;
+}
+
+int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
+                 const uint64_t *hz, DevSched ds, const DevSched *sched_dev, uint64_t *counters,
+                 uint32_t *grid_done, hipStream_t stream) {
+  // With a device-side choice the host does not know the chunk; bound the
+  // piece count with the smallest chunk of any class.
+  const uint32_t bound_chunk = sched_dev ? kChunks[0] : ds.chunk;
+  const uint32_t bound_wgs = sched_dev ? 64u : ds.wgs;
+  const int per_cu = std::min(c->grid_per_cu > 0 ? c->grid_per_cu : default_grid_per_cu(ds, sched_dev != nullptr), c->occ);
+  const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)per_cu;
+  uint64_t i0 = 0;
+  while (i0 < n) {
+    uint64_t i1 = i0, pieces = 0;
+    while (i1 < n && i1 - i0 < kMaxLdsDescs) {
+      uint64_t p = piece_count(hd[i1], hz[i1], bound_chunk, bound_wgs);
+      if (i1 > i0 && pieces + p >= (1ull << 31)) break;
+      pieces += p;
+      i1++;
+    }
+    if (pieces >= (1ull << 31))
+      return fail(c, HICR_EINVAL, "request %llu needs more than 2^31 pieces",
+                  (unsigned long long)i0);
+    DevBatch b{dd + i0, dd + n + i0, dd + 2 * n + i0, dd + 3 * n + i0, (uint32_t)(i1 - i0)};
+    // every wavefront of a workgroup copies its own piece
+    const uint64_t want = (pieces + kCopyBlock / 64 - 1) / (kCopyBlock / 64);
+    uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), cap_grid);
+    hipError_t e = launch_copy(b, ds, sched_dev, counters, grid_done, grid, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
+    i0 = i1;
+  }
+  return HICR_OK;
+}
+
+void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h) {
+  uint64_t *hd = h, *hs = h + n, *hz = h + 2 * n, *hp = h + 3 * n;
+  for (uint64_t i = 0; i < n; i++) {
+    hd[i] = c->slots[d[i].dst_slot].base + d[i].dst_off;
+    hs[i] = c->slots[d[i].src_slot].base + d[i].src_off;
+    hz[i] = d[i].size;
+    hp[i] = (uint64_t)d[i].dst_slot | ((uint64_t)d[i].src_slot << 32);
+  }
 }
 
 // Validate, pack and launch n requests as one submission.
@@ -157,13 +214,7 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, 
   rc = ensure_capacity(c, s, n);
   if (rc != HICR_OK) return rc;
   uint64_t *h = static_cast<uint64_t *>(s.h);
-  uint64_t *hd = h, *hs = h + n, *hz = h + 2 * n, *hp = h + 3 * n;
-  for (uint64_t i = 0; i < n; i++) {
-    hd[i] = c->slots[d[i].dst_slot].base + d[i].dst_off;
-    hs[i] = c->slots[d[i].src_slot].base + d[i].src_off;
-    hz[i] = d[i].size;
-    hp[i] = (uint64_t)d[i].dst_slot | ((uint64_t)d[i].src_slot << 32);
-  }
+  pack_batch(c, d, n, h);
   hipError_t e = hipMemcpyAsync(s.d, s.h, n * 32, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(c, e, "uploading a batch");
   const uint64_t *dd = static_cast<const uint64_t *>(s.d);
@@ -181,30 +232,8 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, 
     e = hipEventRecord(opt->t0, stream);
     if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
   }
-  // With a device-side choice the host does not know the chunk; bound the
-  // piece count with the smallest chunk of any class.
-  const uint32_t bound_chunk = sched_dev ? kChunks[0] : sched.chunk_bytes;
-  const uint32_t bound_wgs = sched_dev ? 64u : sched.wgs_per_desc;
-  const int per_cu = c->grid_per_cu > 0 ? std::min(c->grid_per_cu, c->occ) : c->occ;
-  const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)per_cu;
-  uint64_t i0 = 0;
-  while (i0 < n) {
-    uint64_t i1 = i0, pieces = 0;
-    while (i1 < n && i1 - i0 < kMaxLdsDescs) {
-      uint64_t p = piece_count(hd[i1], hz[i1], bound_chunk, bound_wgs);
-      if (i1 > i0 && pieces + p >= (1ull << 31)) break;
-      pieces += p;
-      i1++;
-    }
-    if (pieces >= (1ull << 31))
-      return fail(c, HICR_EINVAL, "request %llu needs more than 2^31 pieces",
-                  (unsigned long long)i0);
-    DevBatch b{dd + i0, dd + n + i0, dd + 2 * n + i0, dd + 3 * n + i0, (uint32_t)(i1 - i0)};
-    uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(pieces, 1), cap_grid);
-    e = launch_copy(b, ds, sched_dev, counters, s.grid_done, grid, stream);
-    if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
-    i0 = i1;
-  }
+  rc = launch_batch(c, dd, n, h, h + 2 * n, ds, sched_dev, counters, s.grid_done, stream);
+  if (rc != HICR_OK) return rc;
   if (opt && opt->t1) {
     e = hipEventRecord(opt->t1, stream);
     if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
@@ -300,7 +329,7 @@ int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
     c->subs[i].sched_dev = reinterpret_cast<DevSched *>(c->d_words + 64 * i + 16);
   }
   c->def_sched = hicr_sched{64u << 10, 1, 2, HICR_SCHED_FIXED};
-  if (!ok || ensure_counter_capacity(c, 1024) != HICR_OK) {
+  if (!ok || alloc_counters(c) != HICR_OK) {
     hicr_ctx_destroy(c);
     return HICR_EDEVICE;
   }
@@ -312,6 +341,7 @@ int hicr_ctx_destroy(hicr_ctx c) {
   if (!c) return HICR_EINVAL;
   (void)hipSetDevice(c->device);
   wait_all(c);
+  destroy_plans(c);
   destroy_extra(c);
   destroy_sched(c);
   for (Sub &s : c->subs) {
@@ -345,6 +375,13 @@ int hicr_ctx_set_copy_grid(hicr_ctx c, uint32_t wgs_per_cu) {
   return HICR_OK;
 }
 
+int hicr_ctx_set_pairs(hicr_ctx c, uint32_t pair_mask) {
+  if (!c || (pair_mask & ~HICR_PAIRS_ALL)) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  c->pair_mask = pair_mask;
+  return HICR_OK;
+}
+
 int hicr_slot_register(hicr_ctx c, void *ptr, uint64_t size, uint32_t memspace, hicr_slot *out) {
   if (!c || !out) return HICR_EINVAL;
   std::lock_guard<std::mutex> g(c->mu);
@@ -370,11 +407,32 @@ int hicr_slot_register(hicr_ctx c, void *ptr, uint64_t size, uint32_t memspace, 
     if (p - b > alloc || size > alloc - (p - b))
       return fail(c, HICR_ERANGE, "slot extends past the end of its allocation");
   }
-  if (c->slots.size() >= 0xffffffffull) return fail(c, HICR_ENOMEM, "slot ids exhausted");
-  int rc = ensure_counter_capacity(c, (uint32_t)c->slots.size() + 1);
-  if (rc != HICR_OK) return rc;
+  uint64_t dev_addr = reinterpret_cast<uint64_t>(ptr);
+  if (memspace == HICR_MEM_HOST) {
+    // pinned host memory: the device reaches it at its device-side address
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeHost) {
+      (void)hipGetLastError();
+      return fail(c, HICR_EINVAL, "address is not pinned host memory");
+    }
+    void *dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, ptr, 0) != hipSuccess || !dp) {
+      (void)hipGetLastError();
+      return fail(c, HICR_EINVAL, "pinned host memory without a device address");
+    }
+    dev_addr = reinterpret_cast<uint64_t>(dp);
+    void *last = static_cast<char *>(ptr) + (size - 1);
+    void *dlast = nullptr;
+    if (size > 1 && (hipHostGetDevicePointer(&dlast, last, 0) != hipSuccess ||
+                     reinterpret_cast<uint64_t>(dlast) != dev_addr + (size - 1))) {
+      (void)hipGetLastError();
+      return fail(c, HICR_ERANGE, "slot extends past the end of its pinned allocation");
+    }
+  }
+  if (c->slots.size() >= kMaxSlots)
+    return fail(c, HICR_ENOMEM, "at most %u slots per context", kMaxSlots);
   Slot s;
-  s.base = reinterpret_cast<uint64_t>(ptr);
+  s.base = dev_addr;
   s.size = size;
   s.space = memspace;
   s.live = true;
@@ -390,8 +448,12 @@ int hicr_slot_deregister(hicr_ctx c, hicr_slot slot) {
   for (const hicr_desc &d : c->pending)
     if (d.dst_slot == slot || d.src_slot == slot)
       return fail(c, HICR_EBUSY, "slot has unsubmitted transfers; fence first");
+  if (c->slots[slot].plan_refs)
+    return fail(c, HICR_EBUSY, "slot is used by %u plan(s)", c->slots[slot].plan_refs);
+  if (c->slots[slot].dobj_refs)
+    return fail(c, HICR_EBUSY, "slot holds %u published data object(s)", c->slots[slot].dobj_refs);
   (void)hipSetDevice(c->device);
-  if (any_inflight(c) || extra_inflight(c))
+  if (any_inflight(c) || extra_inflight(c) || plans_inflight(c))
     return fail(c, HICR_EBUSY, "transfers in flight; fence first");
   c->slots[slot].live = false;
   return HICR_OK;
@@ -471,7 +533,7 @@ int hicr_fence_slot(hicr_ctx c, hicr_slot slot, uint64_t exp_sent, uint64_t exp_
     bool busy;
     {
       std::lock_guard<std::mutex> g(c->mu);
-      busy = any_inflight(c) || extra_inflight(c);
+      busy = any_inflight(c) || extra_inflight(c) || plans_inflight(c);
     }
     uint64_t s = 0, r = 0;
     int rc = hicr_slot_counters(c, slot, &s, &r);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -11,6 +12,7 @@
 #include "internal.h"
 
 struct hicr_channel_s;
+struct hicr_plan_s;
 
 namespace hicr {
 
@@ -18,6 +20,8 @@ struct Slot {
   uint64_t base = 0;
   uint64_t size = 0;
   uint32_t space = 0;
+  uint32_t plan_refs = 0;  // plans whose requests name this slot
+  uint32_t dobj_refs = 0;  // published data objects inside this slot
   bool live = false;
 };
 
@@ -41,6 +45,7 @@ struct SubmitOpts {
 };
 
 constexpr int kNumSubs = 4;
+constexpr uint32_t kMaxSlots = 1u << 20;  // slots per context (fixed counter table)
 
 struct SchedState;  // autotuned table and device-resident network (sched.cpp)
 
@@ -66,6 +71,7 @@ struct hicr_ctx_s {
   int n_cu = 1;
   int occ = 1;       // copy workgroups per CU that fit
   int grid_per_cu = 0;  // copy workgroups per CU launched (0: all that fit)
+  uint32_t pair_mask = HICR_PAIRS_ALL;  // memory-space pairs memcpy accepts
   std::vector<hicr::Slot> slots;
   uint64_t *d_counters = nullptr;  // [slot] = {sent, recv}
   uint32_t counter_cap = 0;
@@ -78,6 +84,9 @@ struct hicr_ctx_s {
   hicr::SchedState *sched = nullptr;
   int last_learned_sub = -1;  // submission whose class the device chose last
   std::vector<struct hicr_channel_s *> channels;
+  std::vector<struct hicr_plan_s *> plans;
+  std::map<uint64_t, hicr_dobj_handle> dobjs;  // published data objects by id
+  uint64_t next_dobj_id = 1;
   std::vector<hicr::Extra> extra;
   int pump_occ = 0;  // pump workgroups per CU
   hipEvent_t push_ev = nullptr;  // last host-API channel push or network step
@@ -95,11 +104,24 @@ int hip_fail(hicr_ctx c, hipError_t e, const char *what);
 int check_desc(hicr_ctx c, const hicr_desc &d);
 int check_sched(hicr_ctx c, const hicr_sched &s);
 bool any_inflight(hicr_ctx c);
+// Wait for an event: poll briefly, then block.
+hipError_t sync_event(hipEvent_t e);
 int wait_all(hicr_ctx c);
 int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, bool learned,
            hipStream_t stream, uint64_t *bad, const SubmitOpts *opt);
 int flush_pending(hicr_ctx c);
-int ensure_counter_capacity(hicr_ctx c, uint32_t nslots);
+// Resolve requests to the structure of arrays {dst, src, size, slot pair}.
+void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h);
+// Launch the copy kernel over an uploaded batch, one launch per sub-batch of
+// at most kMaxLdsDescs requests (hd/hz: host copies of dst and size).
+int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
+                 const uint64_t *hz, DevSched ds, const DevSched *sched_dev, uint64_t *counters,
+                 uint32_t *grid_done, hipStream_t stream);
+
+// Persistent batch plans (plan.cpp).
+int wait_plans(hicr_ctx c);
+bool plans_inflight(hicr_ctx c);
+void destroy_plans(hicr_ctx c);
 
 // Schedule selection (sched.cpp).  For mode LEARNED with a loaded network
 // *learned is set and the class is picked on the device during submission.

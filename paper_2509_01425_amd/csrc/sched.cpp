@@ -244,7 +244,7 @@ int hicr_last_choice(hicr_ctx c, uint32_t *cls) {
   if (c->last_learned_sub < 0) return fail(c, HICR_EINVAL, "no learned submission yet");
   (void)hipSetDevice(c->device);
   Sub &s = c->subs[c->last_learned_sub];
-  hipError_t e = hipEventSynchronize(s.ev);
+  hipError_t e = sync_event(s.ev);
   DevSched d{};
   if (e == hipSuccess) e = hipMemcpy(&d, s.sched_dev, sizeof d, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(c, e, "reading the chosen class");

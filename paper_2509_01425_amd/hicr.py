@@ -104,6 +104,11 @@ class hicr_serve_stats(ctypes.Structure):
                 ("max_inflight_requests", ctypes.c_uint64), ("wall_ns", ctypes.c_uint64)]
 
 
+class hicr_dobj_handle(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("size", ctypes.c_uint64), ("offset", ctypes.c_uint64),
+                ("slot", ctypes.c_uint32), ("memspace", ctypes.c_uint32)]
+
+
 _u32, _u64, _vp, _int = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
 _pu32, _pu64, _pvp = ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_vp)
 
@@ -115,6 +120,7 @@ _SIGNATURES = {
     "hicr_last_error": (_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "hicr_ctx_set_sched": (_int, [_vp, ctypes.POINTER(hicr_sched)]),
     "hicr_ctx_set_copy_grid": (_int, [_vp, _u32]),
+    "hicr_ctx_set_pairs": (_int, [_vp, _u32]),
     "hicr_slot_register": (_int, [_vp, _vp, _u64, _u32, _pu32]),
     "hicr_slot_deregister": (_int, [_vp, _u32]),
     "hicr_slot_counters": (_int, [_vp, _u32, _pu64, _pu64]),
@@ -122,6 +128,13 @@ _SIGNATURES = {
     "hicr_memcpy_batch": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_sched), _vp, _pu64]),
     "hicr_fence": (_int, [_vp]),
     "hicr_fence_slot": (_int, [_vp, _u32, _u64, _u64, _u64]),
+    "hicr_dobj_publish": (_int, [_vp, _u32, _u64, _u64, _pu64]),
+    "hicr_dobj_get_handle": (_int, [_vp, _u64, ctypes.POINTER(hicr_dobj_handle)]),
+    "hicr_dobj_get": (_int, [_vp, ctypes.POINTER(hicr_dobj_handle), _u32, _u64]),
+    "hicr_dobj_unpublish": (_int, [_vp, _u64]),
+    "hicr_plan_create": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_sched), _pvp, _pu64]),
+    "hicr_plan_launch": (_int, [_vp, _vp]),
+    "hicr_plan_destroy": (_int, [_vp]),
     "hicr_channel_create": (_int, [_vp, ctypes.POINTER(hicr_channel_cfg), _pvp]),
     "hicr_channel_destroy": (_int, [_vp]),
     "hicr_channel_push": (_int, [_vp, _u32, _u32, _u64, _u64]),
@@ -207,6 +220,17 @@ def hicr_ctx_set_copy_grid(ctx, wgs_per_cu: int) -> int:
     return lib().hicr_ctx_set_copy_grid(ctx, wgs_per_cu)
 
 
+def hicr_ctx_set_pairs(ctx, pair_mask: int) -> int:
+    return lib().hicr_ctx_set_pairs(ctx, pair_mask)
+
+
+def PAIR(dst_space: int, src_space: int) -> int:
+    return 1 << (2 * dst_space + src_space)
+
+
+PAIRS_ALL = 0xF
+
+
 def hicr_slot_register(ctx, ptr: int, size: int, memspace: int = MEM_HBM):
     out = _u32()
     rc = lib().hicr_slot_register(ctx, ptr, size, memspace, ctypes.byref(out))
@@ -242,6 +266,44 @@ def hicr_fence(ctx) -> int:
 
 def hicr_fence_slot(ctx, slot: int, exp_sent: int, exp_recv: int, timeout_ns: int) -> int:
     return lib().hicr_fence_slot(ctx, slot, exp_sent, exp_recv, timeout_ns)
+
+
+def hicr_plan_create(ctx, descs: np.ndarray, sched=None):
+    """Returns (rc, plan handle, bad index)."""
+    d = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+    out, bad = _vp(), _u64(0)
+    rc = lib().hicr_plan_create(ctx, d.ctypes.data if d.size else None, d.size,
+                                ctypes.byref(sched) if sched is not None else None,
+                                ctypes.byref(out), ctypes.byref(bad))
+    return rc, out.value, bad.value
+
+
+def hicr_plan_launch(plan, stream: int = 0) -> int:
+    return lib().hicr_plan_launch(plan, stream or None)
+
+
+def hicr_plan_destroy(plan) -> int:
+    return lib().hicr_plan_destroy(plan)
+
+
+def hicr_dobj_publish(ctx, slot: int, offset: int, size: int):
+    out = _u64(0)
+    rc = lib().hicr_dobj_publish(ctx, slot, offset, size, ctypes.byref(out))
+    return rc, out.value
+
+
+def hicr_dobj_get_handle(ctx, obj_id: int):
+    h = hicr_dobj_handle()
+    rc = lib().hicr_dobj_get_handle(ctx, obj_id, ctypes.byref(h))
+    return rc, h
+
+
+def hicr_dobj_get(ctx, handle: hicr_dobj_handle, dst: int, dst_off: int) -> int:
+    return lib().hicr_dobj_get(ctx, ctypes.byref(handle), dst, dst_off)
+
+
+def hicr_dobj_unpublish(ctx, obj_id: int) -> int:
+    return lib().hicr_dobj_unpublish(ctx, obj_id)
 
 
 # --------------------------------------------------------------- channels

@@ -65,3 +65,43 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and every field offset of the header's structs, as the C
+    compiler lays them out, equal the ctypes binding's (and the numpy
+    descriptor dtype's)."""
+    import subprocess
+    structs = {"hicr_sched": H.hicr_sched, "hicr_channel_cfg": H.hicr_channel_cfg,
+               "hicr_stream": H.hicr_stream, "hicr_pump_io": H.hicr_pump_io,
+               "hicr_request": H.hicr_request, "hicr_serve_cfg": H.hicr_serve_cfg,
+               "hicr_serve_stats": H.hicr_serve_stats, "hicr_dobj_handle": H.hicr_dobj_handle}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hicr.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            if f == "pad":
+                continue
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines.append('printf("hicr_desc sizeof %zu\\n", sizeof(hicr_desc));')
+    for f in H.DESC_DTYPE.names:
+        lines.append(f'printf("hicr_desc {f} %zu\\n", offsetof(hicr_desc, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        name, field, v = ln.split()
+        got[(name, field)] = int(v)
+    for name, cls in structs.items():
+        assert got[(name, "sizeof")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            if f != "pad":
+                assert got[(name, f)] == getattr(cls, f).offset, (name, f)
+    assert got[("hicr_desc", "sizeof")] == H.DESC_DTYPE.itemsize
+    for f in H.DESC_DTYPE.names:
+        assert got[("hicr_desc", f)] == H.DESC_DTYPE.fields[f][1], f

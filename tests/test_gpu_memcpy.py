@@ -226,7 +226,9 @@ def test_rejections_enqueue_nothing(env):
     d[:] = [(sb, sa, 0, 0, 8), (sb, sa, 8, 60, 8), (sb, sa, 16, 0, 4)]
     assert H.hicr_memcpy_batch(ctx, d) == (H.ERANGE, 1)
     d[1] = (sh, sa, 0, 0, 4)
+    assert H.hicr_ctx_set_pairs(ctx, H.PAIR(H.MEM_HBM, H.MEM_HBM)) == H.OK
     assert H.hicr_memcpy_batch(ctx, d) == (H.EUNSUPPORTED, 1)
+    assert H.hicr_ctx_set_pairs(ctx, H.PAIRS_ALL) == H.OK
     d[1] = (sb, 12345, 0, 0, 4)
     assert H.hicr_memcpy_batch(ctx, d) == (H.EBADSLOT, 1)
     assert H.hicr_memcpy(ctx, sb, 0, sa, 2**64 - 1, 2) == H.ERANGE
