@@ -444,10 +444,11 @@ def bench_tiny(torch, H, reps=1000, warmup=50):
     out = {"workload": "tiny: 64 packed slots (1..64 KiB), 256 requests of 1..8 KiB, "
                        "submit + fence per rep", "bytes_rw": moved, "reps": reps,
            "memcpy_batch": lat(submit)}
-    rc, plan, _ = H.hicr_plan_create(ctx, d, sched)
-    assert rc == H.OK, H.hicr_last_error(ctx)
-    out["plan_replay"] = lat(lambda: H.hicr_plan_launch(plan))
-    assert H.hicr_plan_destroy(plan) == H.OK
+    for name, flags in (("plan_replay", 0), ("plan_graph_replay", H.PLAN_GRAPH)):
+        rc, plan, _ = H.hicr_plan_create(ctx, d, sched, flags)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        out[name] = lat(lambda: H.hicr_plan_launch(plan))
+        assert H.hicr_plan_destroy(plan) == H.OK
     H.hicr_ctx_destroy(ctx)
     return out
 
@@ -498,10 +499,11 @@ def bench_halo(torch, H, N=704, Py=2, Pz=4, iters=200, reps=3):
            "requests": len(d), "bytes_rw": moved,
            "autotune_ms": [round(float(t), 4) for t in times], "best_class": int(best),
            "memcpy_batch": run(lambda: H.hicr_memcpy_batch(ctx, d, sched))}
-    rc, plan, _ = H.hicr_plan_create(ctx, d, sched)
-    assert rc == H.OK, H.hicr_last_error(ctx)
-    out["plan_replay"] = run(lambda: H.hicr_plan_launch(plan))
-    assert H.hicr_plan_destroy(plan) == H.OK
+    for name, flags in (("plan_replay", 0), ("plan_graph_replay", H.PLAN_GRAPH)):
+        rc, plan, _ = H.hicr_plan_create(ctx, d, sched, flags)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        out[name] = run(lambda: H.hicr_plan_launch(plan))
+        assert H.hicr_plan_destroy(plan) == H.OK
     H.hicr_ctx_destroy(ctx)
     del pool
     torch.cuda.empty_cache()

@@ -170,9 +170,10 @@ int hicr_fence_slot(hicr_ctx ctx, hicr_slot slot, uint64_t exp_sent, uint64_t ex
 
 /* ------------------------------------------ persistent batch plans (growth) */
 /* Sec. 3.1.4 memcpy batches that repeat unchanged (a halo exchange, a fixed
- * gather): the batch is validated, resolved to addresses and uploaded once,
- * and its fused copy launches are captured in a HIP graph; every
- * hicr_plan_launch replays the graph.  One replay moves every request once
+ * gather): the batch is validated, resolved to addresses and uploaded once;
+ * every hicr_plan_launch queues its fused copy launches and counter kernel
+ * again -- directly, or, with HICR_PLAN_GRAPH, as one launch of a HIP graph
+ * captured at creation.  One replay moves every request once
  * and raises each request's sent/recv counters once, like one
  * hicr_memcpy_batch of the same requests; hicr_fence (and fence_slot) wait
  * for replays as for any other transfer.
@@ -186,8 +187,10 @@ int hicr_fence_slot(hicr_ctx ctx, hicr_slot slot, uint64_t exp_sent, uint64_t ex
  * previous one first waits for the previous replay.  Slot contents may change
  * between replays; slot addresses may not (they are resolved at creation). */
 typedef struct hicr_plan_s *hicr_plan;
+#define HICR_PLAN_GRAPH 1u /* flags: replay as one captured HIP graph */
+/* flags other than HICR_PLAN_GRAPH -> HICR_EINVAL. */
 int hicr_plan_create(hicr_ctx ctx, const hicr_desc *d, uint64_t n, const hicr_sched *s_or_null,
-                     hicr_plan *out, uint64_t *bad_index_or_null);
+                     uint32_t flags, hicr_plan *out, uint64_t *bad_index_or_null);
 /* Replay once on `stream` (NULL: the context stream).  Asynchronous. */
 int hicr_plan_launch(hicr_plan plan, void *stream);
 /* Wait for the plan's last replay, then free it and release its slots. */
@@ -359,7 +362,11 @@ typedef struct {
   uint64_t n_msgs;
   uint32_t *trace_dev;   /* optional device array: for every consumed message, its
                             stream index; channels in order of first appearance in
-                            the stream list, each in the order its consumer took them */
+                            the stream list.  A locking MPSC channel's part is the
+                            order its consumer took the messages from the shared
+                            ring; SPSC and non-locking MPSC rings are consumed
+                            independently, so their part lists producer 0's
+                            messages, then producer 1's, ...                     */
   uint64_t *ts_dev;      /* optional device array [2 * n_msgs]: publish time, then
                             consume time of every message (100 MHz device clock)    */
   uint64_t timeout_ns;   /* a wait that sees no progress for this long ends the
@@ -367,8 +374,11 @@ typedef struct {
 } hicr_pump_io;
 
 /* Run every stream through its device-endpoint channel in one persistent
- * launch on `stream`: one GPU wave per producer stream, one workgroup per
- * consumer.  Validated on the host (slots, ranges, sizes, one stream per
+ * launch on `stream`: one GPU wave per producer stream; one consumer
+ * workgroup per locking MPSC channel (its shared ring), and the rings that
+ * have a single producer (SPSC rings, non-locking MPSC sub-rings) spread over
+ * the remaining workgroups the device holds, balanced by bytes -- the
+ * consumer of a non-locking MPSC channel is such a team.  Validated on the host (slots, ranges, sizes, one stream per
  * (channel, producer)); HICR_EINVAL if the launch would not fit on the device
  * at once.  Asynchronous; hicr_fence reports a time-out or abort.  A channel
  * has one producer and one consumer per ring: two pump launches that drive

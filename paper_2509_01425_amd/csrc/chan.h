@@ -46,13 +46,18 @@ struct DevRing {
 
 enum : uint32_t { kModeSpsc = 0, kModeMpscLock = 1, kModeMpscNoLock = 2 };
 
+// One consumer unit (one workgroup).  kModeMpscLock: the shared ring of a
+// locking MPSC channel, K producers told apart by the entry's producer tag.
+// kModeSpsc: n_rings independent rings, each with exactly one producer stream
+// (SPSC rings and non-locking MPSC sub-rings, possibly of different
+// channels); ring q belongs to stream stream_of_prod[prod_stream_base + q].
 struct DevChannel {
   uint32_t mode;
-  uint32_t n_rings;     // 1, or K for non-locking MPSC
-  uint32_t first_ring;  // index into the ring table
-  uint32_t K;           // producers
-  uint64_t total_msgs;  // messages the consumer must take
-  uint64_t trace_base;  // first trace slot of this channel
+  uint32_t n_rings;
+  uint32_t first_ring;  // index into the ring table (the unit's rings are consecutive)
+  uint32_t K;           // producers (== n_rings for independent rings)
+  uint64_t total_msgs;  // messages the unit must take
+  uint64_t trace_base;  // first trace slot (locking MPSC)
   uint32_t prod_stream_base;  // index into stream_of_prod: K entries
   uint32_t pad;
 };
@@ -67,10 +72,11 @@ struct DevStream {
   uint64_t first_msg;  // index into msg_off/msg_size
   uint64_t n_msgs;
   uint64_t out_bytes;  // sum of the stream's message sizes (bound of its output)
+  uint64_t trace_base; // first trace slot of the stream (rings consumed on their own)
 };
 
 // Per-workgroup role: kind 0 = up to four producer waves (ids = streams),
-// kind 1 = one consumer (ids[0] = channel).
+// kind 1 = one consumer unit (ids[0] = unit).
 struct DevRole {
   uint32_t kind;
   uint32_t count;

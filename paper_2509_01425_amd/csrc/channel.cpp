@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <queue>
 #include <utility>
 #include <vector>
 
@@ -365,27 +366,83 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
       return fail(c, HICR_ERANGE, "stream %u: output smaller than its %llu bytes", i,
                   (unsigned long long)total);
   }
-  const uint32_t nch = (uint32_t)chans.size();
-  const uint32_t n_wgs = (n + 3) / 4 + nch;
   if (n == 0) return HICR_OK;
-  if ((uint64_t)n_wgs > (uint64_t)c->n_cu * (uint64_t)c->pump_occ)
-    return fail(c, HICR_EINVAL, "%u workgroups do not fit the device at once (%d x %d)", n_wgs,
-                c->n_cu, c->pump_occ);
+  // Consumer units.  A locking MPSC channel's shared ring is one unit (one
+  // consumer, one total order).  Every other ring -- an SPSC channel's ring or
+  // a non-locking MPSC producer's sub-ring -- has exactly one producer and is
+  // consumed on its own; such rings are spread over as many consumer
+  // workgroups as the device still holds, balanced by bytes (longest first),
+  // so one channel's producers do not all wait on one workgroup.
+  const uint32_t prod_wgs = (n + 3) / 4;
+  const uint64_t cap = (uint64_t)c->n_cu * (uint64_t)c->pump_occ;
+  std::vector<uint64_t> stream_bytes(n, 0);
+  for (uint32_t i = 0; i < n; i++)
+    for (uint64_t j = st[i].first_msg; j < st[i].first_msg + st[i].n_msgs; j++)
+      stream_bytes[i] += msg_size[j];
+  std::vector<uint64_t> chan_trace(chans.size());
+  std::vector<uint64_t> stream_trace(n, 0);
+  uint64_t trace_total = 0;
+  for (uint32_t k = 0; k < chans.size(); k++) {
+    chan_trace[k] = trace_total;
+    for (uint32_t p = 0; p < chans[k]->cfg.producers; p++) {
+      auto it = prod_stream.find(std::make_pair(chans[k], p));
+      if (it == prod_stream.end()) continue;
+      stream_trace[it->second] = trace_total;  // independent rings: producer after producer
+      trace_total += st[it->second].n_msgs;
+    }
+  }
+  uint32_t n_lock = 0;
+  std::vector<uint32_t> indep;  // streams whose ring is consumed on its own
+  for (uint32_t k = 0; k < chans.size(); k++) {
+    if (chans[k]->cfg.mode == HICR_CH_MPSC_LOCK) {
+      n_lock++;
+      continue;
+    }
+    for (uint32_t p = 0; p < chans[k]->cfg.producers; p++) {
+      auto it = prod_stream.find(std::make_pair(chans[k], p));
+      if (it != prod_stream.end()) indep.push_back(it->second);
+    }
+  }
+  const uint64_t min_units = (indep.size() + kMaxProducers - 1) / kMaxProducers;
+  if ((uint64_t)prod_wgs + n_lock + min_units > cap)
+    return fail(c, HICR_EINVAL, "%llu workgroups do not fit the device at once (%d x %d)",
+                (unsigned long long)(prod_wgs + n_lock + min_units), c->n_cu, c->pump_occ);
+  const uint32_t n_indep_units =
+      (uint32_t)std::min<uint64_t>(indep.size(), cap - prod_wgs - n_lock);
+  // longest first onto the least loaded unit (at most kMaxProducers rings each)
+  std::vector<std::vector<uint32_t>> unit_streams(n_indep_units);
+  {
+    std::vector<uint32_t> order = indep;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return stream_bytes[x] > stream_bytes[y]; });
+    using Load = std::pair<uint64_t, uint32_t>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (uint32_t u = 0; u < n_indep_units; u++) heap.push(Load(0, u));
+    for (uint32_t sid : order) {
+      Load l = heap.top();
+      heap.pop();
+      unit_streams[l.second].push_back(sid);
+      l.first += stream_bytes[sid] + 1;
+      if (unit_streams[l.second].size() < kMaxProducers) heap.push(l);
+    }
+  }
   // tables
   std::vector<DevRing> rings;
-  std::vector<DevChannel> dch(nch);
+  std::vector<DevChannel> dch;
   std::vector<uint32_t> sop;
-  uint64_t trace_total = 0;
-  for (uint32_t k = 0; k < nch; k++) {
+  std::vector<DevStream> ds(n);
+  std::vector<uint32_t> unit_of(n, 0), ring_of(n, 0);
+  for (uint32_t k = 0; k < chans.size(); k++) {
     hicr_channel ch = chans[k];
-    DevChannel &d = dch[k];
-    d.mode = ch->cfg.mode;
-    d.n_rings = ch->n_rings;
+    if (ch->cfg.mode != HICR_CH_MPSC_LOCK) continue;
+    DevChannel d{};
+    d.mode = kModeMpscLock;
+    d.n_rings = 1;
     d.first_ring = (uint32_t)rings.size();
     d.K = ch->cfg.producers;
-    d.total_msgs = 0;
+    d.trace_base = chan_trace[k];
     d.prod_stream_base = (uint32_t)sop.size();
-    for (uint32_t r = 0; r < ch->n_rings; r++) rings.push_back(dev_ring(ch, r));
+    rings.push_back(dev_ring(ch, 0));
     uint32_t any = 0;
     for (uint32_t p = 0; p < d.K; p++) {
       auto it = prod_stream.find(std::make_pair(ch, p));
@@ -394,27 +451,44 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
     for (uint32_t p = 0; p < d.K; p++) {
       auto it = prod_stream.find(std::make_pair(ch, p));
       sop.push_back(it != prod_stream.end() ? it->second : any);
+      if (it != prod_stream.end()) {
+        unit_of[it->second] = (uint32_t)dch.size();
+        ring_of[it->second] = d.first_ring;
+        d.total_msgs += st[it->second].n_msgs;
+      }
     }
+    dch.push_back(d);
   }
-  std::vector<DevStream> ds(n);
+  for (const auto &us : unit_streams) {
+    DevChannel d{};
+    d.mode = kModeSpsc;  // independent single-producer rings
+    d.n_rings = (uint32_t)us.size();
+    d.first_ring = (uint32_t)rings.size();
+    d.K = d.n_rings;
+    d.prod_stream_base = (uint32_t)sop.size();
+    for (uint32_t sid : us) {
+      hicr_channel ch = st[sid].channel;
+      const uint32_t r = ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? st[sid].producer : 0;
+      unit_of[sid] = (uint32_t)dch.size();
+      ring_of[sid] = (uint32_t)rings.size();
+      rings.push_back(dev_ring(ch, r));
+      sop.push_back(sid);
+      d.total_msgs += st[sid].n_msgs;
+    }
+    dch.push_back(d);
+  }
+  const uint32_t nch = (uint32_t)dch.size();
+  const uint32_t n_wgs = prod_wgs + nch;
   for (uint32_t i = 0; i < n; i++) {
-    hicr_channel ch = st[i].channel;
-    const uint32_t k = chan_idx[ch];
-    ds[i].channel = k;
+    ds[i].channel = unit_of[i];
     ds[i].producer = st[i].producer;
-    ds[i].ring = dch[k].first_ring + (ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? st[i].producer : 0);
+    ds[i].ring = ring_of[i];
     ds[i].src_base = st[i].src_base;
     ds[i].out_base = st[i].out_base;
     ds[i].first_msg = st[i].first_msg;
     ds[i].n_msgs = st[i].n_msgs;
-    ds[i].out_bytes = 0;
-    for (uint64_t j = st[i].first_msg; j < st[i].first_msg + st[i].n_msgs; j++)
-      ds[i].out_bytes += msg_size[j];
-    dch[k].total_msgs += st[i].n_msgs;
-  }
-  for (uint32_t k = 0; k < nch; k++) {
-    dch[k].trace_base = trace_total;
-    trace_total += dch[k].total_msgs;
+    ds[i].out_bytes = stream_bytes[i];
+    ds[i].trace_base = stream_trace[i];
   }
   if (trace_dev) {
     int rc = check_dev_range(c, trace_dev, trace_total * 4, "trace_dev");

@@ -163,20 +163,23 @@ __device__ void seg_copy(const Seg *sg, uint32_t nseg, uint64_t total_v, uint32_
       *(GLOBAL unsigned char *)(g.d + o) = *(const GLOBAL unsigned char *)(g.s + o);
     }
   }
+  // A thread's vectors only grow (within a round with k, across rounds with
+  // b), so one cursor on the segment of the round's first vector is kept and
+  // stepped forward -- a round usually stays in one segment -- instead of a
+  // search before every load.
+  uint32_t c0 = 0;
   for (uint64_t b = 0; b < total_v; b += (uint64_t)TEAM * U) {
     v4u r[U];
     uint64_t da[U];
+    uint32_t c = c0;
 #pragma unroll
     for (int k = 0; k < U; k++) {
       const uint64_t v = b + t + (uint64_t)k * TEAM;
       da[k] = 0;
       if (v < total_v) {
-        uint32_t lo = 0, hi = nseg;  // last segment with v0 <= v
-        while (hi - lo > 1) {
-          uint32_t mid = (lo + hi) >> 1;
-          if (sg[mid].v0 <= v) lo = mid; else hi = mid;
-        }
-        const Seg &g = sg[lo];
+        while (c + 1 < nseg && sg[c + 1].v0 <= v) c++;  // last segment with v0 <= v
+        if (k == 0) c0 = c;
+        const Seg &g = sg[c];
         const uint64_t w = v - g.v0;
         r[k] = *(const GLOBAL v4u_any *)(g.s + (g.a0 - g.d) + 16 * w);
         da[k] = g.a0 + 16 * w;
@@ -305,11 +308,12 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
   // below touches LDS only
   __shared__ uint64_t s_rpay[kMaxProducers], s_rent[kMaxProducers], s_rcoord[kMaxProducers];
   __shared__ uint64_t s_pout[kMaxProducers], s_pbytes[kMaxProducers];
-  __shared__ uint64_t s_pfirst[kMaxProducers], s_pn[kMaxProducers];
+  __shared__ uint64_t s_pfirst[kMaxProducers], s_pn[kMaxProducers], s_ptrace[kMaxProducers];
+  __shared__ uint64_t s_rP[kMaxProducers], s_rE[kMaxProducers];
   __shared__ uint32_t s_psid[kMaxProducers];
   const DevChannel ch = a.chans[cid];
+  const bool locking = ch.mode == kModeMpscLock;
   const uint32_t lane = tid & 63, wave = tid >> 6;
-  const uint64_t P = a.rings[ch.first_ring].P, E = a.rings[ch.first_ring].E;
   for (uint32_t i = tid; i < ch.n_rings; i += kPumpBlock) {
     const DevRing rg = a.rings[ch.first_ring + i];
     const uint64_t c = rg.coord + offsetof(RingCoord, cons);
@@ -318,6 +322,8 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
     s_rpay[i] = rg.payload;
     s_rent[i] = rg.entries;
     s_rcoord[i] = rg.coord;
+    s_rP[i] = rg.P;
+    s_rE[i] = rg.E;
   }
   for (uint32_t p = tid; p < ch.K; p += kPumpBlock) {
     const uint32_t sid = a.stream_of_prod[ch.prod_stream_base + p];
@@ -327,6 +333,7 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
     s_pbytes[p] = so.out_bytes;
     s_pfirst[p] = so.first_msg;
     s_pn[p] = so.n_msgs;
+    s_ptrace[p] = so.trace_base;
     s_outpos[p] = 0;
     s_cnt[p] = 0;
   }
@@ -383,8 +390,10 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
       }
     }
     __syncthreads();
-    if (tid < k)
-      s_ent[tid] = *(const GLOBAL uint64_t *)(s_rent[s_ring_of[tid]] + 8 * (s_idx_of[tid] % E));
+    if (tid < k) {
+      const uint32_t ri = s_ring_of[tid];
+      s_ent[tid] = *(const GLOBAL uint64_t *)(s_rent[ri] + 8 * (s_idx_of[tid] % s_rE[ri]));
+    }
     __syncthreads();
     if (tid == 0) {
       // plan the copies; entries are checked against the plan first, so a
@@ -395,7 +404,10 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
         const uint32_t ri = s_ring_of[i];
         const uint64_t e = s_ent[i];
         const uint64_t sz = e & kEntrySizeMask;
-        const uint32_t p = (uint32_t)(e >> 48) % ch.K;
+        // a shared ring names its producer in the entry; an independent ring
+        // has one producer
+        const uint32_t p = locking ? (uint32_t)(e >> 48) % ch.K : ri;
+        const uint64_t P = s_rP[ri];
         if (sz > P || s_outpos[p] + sz > s_pbytes[p] || s_cnt[p] >= s_pn[p]) {
           bad = 1;
           break;
@@ -407,7 +419,8 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
         if (sz > first) s_seg[nseg++] = make_seg(dst + first, s_rpay[ri], sz - first);
         s_rbytes[ri] += sz;
         s_outpos[p] += sz;
-        if (a.trace) a.trace[ch.trace_base + done + i] = s_psid[p];
+        if (a.trace)
+          a.trace[locking ? ch.trace_base + done + i : s_ptrace[p] + s_cnt[p]] = s_psid[p];
         if (a.ts_pop) a.ts_pop[s_pfirst[p] + s_cnt[p]] = wall_clock64();
         s_cnt[p] += 1;
       }

@@ -54,9 +54,12 @@ __host__ __device__ inline uint64_t piece_count(uint64_t dst, uint64_t size, uin
 
 // Launch the fused copy kernel over one sub-batch (n <= kMaxLdsDescs).
 // sched_dev, when not null, overrides `s` with a device-resident choice.
-hipError_t launch_copy(const DevBatch &b, DevSched s, const DevSched *sched_dev,
-                       uint64_t *counters, uint32_t *grid_done, uint32_t grid,
+hipError_t launch_copy(const DevBatch &b, DevSched s, const DevSched *sched_dev, uint32_t grid,
                        hipStream_t stream);
+// Raise the slot counters of n requests (slots[i] = dst | src << 32); queued
+// after the copy launches of the same requests on the same stream.
+hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters,
+                        hipStream_t stream);
 // Workgroups of the copy kernel that one CU holds at once.
 int copy_occupancy(int *wgs_per_cu);
 

@@ -2,11 +2,13 @@
 //
 // A plan is a batch of memcpy requests (HiCR Sec. 3.1.4) that a caller
 // repeats unchanged.  Validation, address resolution and the upload happen
-// once; the fused copy launches (one per sub-batch of at most 4,096
-// requests) are captured from a private stream into a graph, and each replay
-// is one hipGraphLaunch.  The graph holds kernel nodes only: the
-// finished-workgroup word that the copy kernel uses is zeroed once here and
-// returned to zero by the last workgroup of every launch.
+// once.  A replay queues the fused copy launches (one per sub-batch of at
+// most 4,096 requests) and the counter kernel again, either directly or --
+// HICR_PLAN_GRAPH -- as one hipGraphLaunch of those launches captured from a
+// private stream at creation.  The graph holds kernel nodes only; nothing in
+// it needs clearing between replays.  (Measured on gfx950 with ROCm 7: a
+// graph of two or five kernel nodes launches slower than the same kernels
+// queued directly, so direct replay is the default.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,9 +23,12 @@ struct hicr_plan_s {
   hicr_ctx c = nullptr;
   uint64_t n = 0;
   void *d = nullptr;          // device SoA {dst, src, size, slot pair}, 32 B per request
-  char *words = nullptr;      // grid_done (offset 0), device-chosen schedule (offset 16)
+  char *words = nullptr;      // device-chosen schedule (offset 16)
   hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec = nullptr;  // HICR_PLAN_GRAPH
+  std::vector<uint64_t> h;        // host copy of the packed requests (direct replay)
+  DevSched ds{};
+  const DevSched *sched_dev = nullptr;
   hipEvent_t ev = nullptr;    // end of the last replay
   hipStream_t last = nullptr; // stream of the last replay
   bool launched = false;
@@ -86,8 +91,8 @@ void destroy_plans(hicr_ctx c) {
 extern "C" {
 
 int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched *s,
-                     hicr_plan *out, uint64_t *bad) {
-  if (!c || !out || (n && !d)) return HICR_EINVAL;
+                     uint32_t flags, hicr_plan *out, uint64_t *bad) {
+  if (!c || !out || (n && !d) || (flags & ~HICR_PLAN_GRAPH)) return HICR_EINVAL;
   *out = nullptr;
   std::lock_guard<std::mutex> g(c->mu);
   (void)hipSetDevice(c->device);
@@ -153,21 +158,25 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
     }
     sched_dev = choice;
   }
-  e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
-  if (e == hipSuccess) {
-    uint32_t *grid_done = reinterpret_cast<uint32_t *>(p->words);
-    rc = launch_batch(c, dd, n, h.data(), h.data() + 2 * n, ds, sched_dev, c->d_counters,
-                      grid_done, cs);
-    hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(cs, &graph);
-    p->graph = graph;
-    if (rc == HICR_OK && e2 != hipSuccess) rc = hip_fail(c, e2, "capturing a plan");
-    if (rc == HICR_OK) {
-      e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) rc = hip_fail(c, e, "instantiating a plan");
+  p->ds = ds;
+  p->sched_dev = sched_dev;
+  if (flags & HICR_PLAN_GRAPH) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      rc = launch_batch(c, dd, n, h.data(), h.data() + 2 * n, ds, sched_dev, c->d_counters, cs);
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(cs, &graph);
+      p->graph = graph;
+      if (rc == HICR_OK && e2 != hipSuccess) rc = hip_fail(c, e2, "capturing a plan");
+      if (rc == HICR_OK) {
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = hip_fail(c, e, "instantiating a plan");
+      }
+    } else {
+      rc = hip_fail(c, e, "capturing a plan");
     }
   } else {
-    rc = hip_fail(c, e, "capturing a plan");
+    p->h.swap(h);
   }
   (void)hipStreamDestroy(cs);
   if (rc != HICR_OK) {
@@ -187,7 +196,14 @@ int hicr_plan_launch(hicr_plan p, void *stream) {
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   hipError_t e = hipSuccess;
   if (p->launched && s != p->last) e = hipStreamWaitEvent(s, p->ev, 0);
-  if (e == hipSuccess) e = hipGraphLaunch(p->exec, s);
+  if (e == hipSuccess && p->exec) {
+    e = hipGraphLaunch(p->exec, s);
+  } else if (e == hipSuccess && p->n) {
+    const uint64_t *dd = static_cast<const uint64_t *>(p->d);
+    int rc = launch_batch(c, dd, p->n, p->h.data(), p->h.data() + 2 * p->n, p->ds, p->sched_dev,
+                          c->d_counters, s);
+    if (rc != HICR_OK) return rc;
+  }
   if (e == hipSuccess) e = hipEventRecord(p->ev, s);
   if (e != hipSuccess) return hip_fail(c, e, "launching a plan");
   p->launched = true;

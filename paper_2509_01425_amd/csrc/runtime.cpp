@@ -155,7 +155,7 @@ int default_grid_per_cu(const DevSched &ds, bool device_choice) {
 
 int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
                  const uint64_t *hz, DevSched ds, const DevSched *sched_dev, uint64_t *counters,
-                 uint32_t *grid_done, hipStream_t stream) {
+                 hipStream_t stream) {
   // With a device-side choice the host does not know the chunk; bound the
   // piece count with the smallest chunk of any class.
   const uint32_t bound_chunk = sched_dev ? kChunks[0] : ds.chunk;
@@ -178,9 +178,13 @@ int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
     // every wavefront of a workgroup copies its own piece
     const uint64_t want = (pieces + kCopyBlock / 64 - 1) / (kCopyBlock / 64);
     uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), cap_grid);
-    hipError_t e = launch_copy(b, ds, sched_dev, counters, grid_done, grid, stream);
+    hipError_t e = launch_copy(b, ds, sched_dev, grid, stream);
     if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
     i0 = i1;
+  }
+  if (counters) {
+    hipError_t e = launch_count(dd + 3 * n, n, counters, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launching the counter kernel");
   }
   return HICR_OK;
 }
@@ -232,7 +236,7 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, 
     e = hipEventRecord(opt->t0, stream);
     if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
   }
-  rc = launch_batch(c, dd, n, h, h + 2 * n, ds, sched_dev, counters, s.grid_done, stream);
+  rc = launch_batch(c, dd, n, h, h + 2 * n, ds, sched_dev, counters, stream);
   if (rc != HICR_OK) return rc;
   if (opt && opt->t1) {
     e = hipEventRecord(opt->t1, stream);
@@ -325,7 +329,6 @@ int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
   if (ok && (pump_occupancy(&c->pump_occ) != 0 || c->pump_occ < 1)) c->pump_occ = 1;
   for (int i = 0; ok && i < kNumSubs; i++) {
     ok = hipEventCreateWithFlags(&c->subs[i].ev, hipEventDisableTiming) == hipSuccess;
-    c->subs[i].grid_done = reinterpret_cast<uint32_t *>(c->d_words + 64 * i);
     c->subs[i].sched_dev = reinterpret_cast<DevSched *>(c->d_words + 64 * i + 16);
   }
   c->def_sched = hicr_sched{64u << 10, 1, 2, HICR_SCHED_FIXED};

@@ -33,7 +33,6 @@ struct Sub {
   uint64_t cap = 0;
   hipEvent_t ev = nullptr;
   bool inflight = false;
-  uint32_t *grid_done = nullptr;
   DevSched *sched_dev = nullptr;  // schedule chosen on the device (learned mode)
 };
 
@@ -75,7 +74,7 @@ struct hicr_ctx_s {
   std::vector<hicr::Slot> slots;
   uint64_t *d_counters = nullptr;  // [slot] = {sent, recv}
   uint32_t counter_cap = 0;
-  char *d_words = nullptr;  // small device words (grid_done per submission)
+  char *d_words = nullptr;  // small device words (device-chosen schedule per submission)
   uint64_t *h_read = nullptr;  // pinned read-back buffer
   hicr::Sub subs[hicr::kNumSubs];
   int next_sub = 0;
@@ -116,7 +115,7 @@ void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h);
 // at most kMaxLdsDescs requests (hd/hz: host copies of dst and size).
 int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
                  const uint64_t *hz, DevSched ds, const DevSched *sched_dev, uint64_t *counters,
-                 uint32_t *grid_done, hipStream_t stream);
+                 hipStream_t stream);
 
 // Persistent batch plans (plan.cpp).
 int wait_plans(hicr_ctx c);

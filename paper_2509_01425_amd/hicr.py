@@ -132,7 +132,7 @@ _SIGNATURES = {
     "hicr_dobj_get_handle": (_int, [_vp, _u64, ctypes.POINTER(hicr_dobj_handle)]),
     "hicr_dobj_get": (_int, [_vp, ctypes.POINTER(hicr_dobj_handle), _u32, _u64]),
     "hicr_dobj_unpublish": (_int, [_vp, _u64]),
-    "hicr_plan_create": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_sched), _pvp, _pu64]),
+    "hicr_plan_create": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_sched), _u32, _pvp, _pu64]),
     "hicr_plan_launch": (_int, [_vp, _vp]),
     "hicr_plan_destroy": (_int, [_vp]),
     "hicr_channel_create": (_int, [_vp, ctypes.POINTER(hicr_channel_cfg), _pvp]),
@@ -268,12 +268,15 @@ def hicr_fence_slot(ctx, slot: int, exp_sent: int, exp_recv: int, timeout_ns: in
     return lib().hicr_fence_slot(ctx, slot, exp_sent, exp_recv, timeout_ns)
 
 
-def hicr_plan_create(ctx, descs: np.ndarray, sched=None):
+PLAN_GRAPH = 1
+
+
+def hicr_plan_create(ctx, descs: np.ndarray, sched=None, flags: int = 0):
     """Returns (rc, plan handle, bad index)."""
     d = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
     out, bad = _vp(), _u64(0)
     rc = lib().hicr_plan_create(ctx, d.ctypes.data if d.size else None, d.size,
-                                ctypes.byref(sched) if sched is not None else None,
+                                ctypes.byref(sched) if sched is not None else None, flags,
                                 ctypes.byref(out), ctypes.byref(bad))
     return rc, out.value, bad.value
 

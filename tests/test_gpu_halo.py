@@ -42,7 +42,7 @@ def test_small_grid_plan_replays(env):
     torch, H, wd, ctx = env
     N, Py, Pz = 37, 2, 3
     pool, slots, d, dd, sb = _rig(torch, H, ctx, N, Py, Pz)
-    rc, plan, _ = H.hicr_plan_create(ctx, dd, H.hicr_sched_class(0)[1])
+    rc, plan, _ = H.hicr_plan_create(ctx, dd, H.hicr_sched_class(0)[1], H.PLAN_GRAPH)
     assert rc == H.OK, H.hicr_last_error(ctx)
     L = Py * Pz * sb
     for k in range(3):

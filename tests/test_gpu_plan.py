@@ -54,16 +54,17 @@ def _oracle_pool(bases, sizes, descs, seed, pool_len):
     return host
 
 
-@pytest.mark.parametrize("cls", [0, 5, 11])
-def test_tiny_plan_every_replay_matches_oracle(env, cls):
+@pytest.mark.parametrize("cls,flags", [(0, 0), (5, 1), (11, 0), (11, 1)])
+def test_tiny_plan_every_replay_matches_oracle(env, cls, flags):
+    """Direct replay (flags 0) and graph replay (HICR_PLAN_GRAPH)."""
     torch, H, wd, ctx = env
     bases, sizes, pool_len, descs, pool, slots, d = _tiny_rig(torch, H, ctx)
-    rc, plan, bad = H.hicr_plan_create(ctx, d, H.hicr_sched_class(cls)[1])
+    rc, plan, bad = H.hicr_plan_create(ctx, d, H.hicr_sched_class(cls)[1], flags)
     assert rc == H.OK, H.hicr_last_error(ctx)
     base_ctr = np.array([H.hicr_slot_counters(ctx, int(s))[1:] for s in slots], np.uint64)
     per = oracle_counters(descs, len(slots))
     for k in range(1, 6):
-        seed = 3000 + 10 * cls + k
+        seed = 3000 + 10 * cls + 100 * flags + k
         _say("plan replay", cls, k)
         wd.fill(pool.data_ptr(), pool_len, seed)
         torch.cuda.synchronize()
@@ -81,8 +82,9 @@ def test_tiny_plan_every_replay_matches_oracle(env, cls):
         assert H.hicr_slot_deregister(ctx, int(s)) == H.OK
 
 
-def test_plan_split_launches_and_stream_switch(env):
-    """10,001 requests (three captured launches), replayed alternately on two
+@pytest.mark.parametrize("flags", [0, 1])
+def test_plan_split_launches_and_stream_switch(env, flags):
+    """10,001 requests (three copy launches), replayed alternately on two
     streams: each replay waits for the previous one."""
     torch, H, wd, ctx = env
     g = np.random.default_rng(8)
@@ -100,12 +102,12 @@ def test_plan_split_launches_and_stream_switch(env):
     d = np.zeros(n, dtype=H.DESC_DTYPE)
     d["dst_slot"], d["src_slot"] = a, b
     d["dst_off"], d["src_off"], d["size"] = dst, src - src_base, sz
-    rc, plan, _ = H.hicr_plan_create(ctx, d, H.hicr_sched_class(1)[1])
+    rc, plan, _ = H.hicr_plan_create(ctx, d, H.hicr_sched_class(1)[1], flags)
     assert rc == H.OK, H.hicr_last_error(ctx)
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
     od = d.copy()
     for k in range(4):
-        seed = 4100 + k
+        seed = 4100 + 10 * flags + k
         _say("split plan replay", k)
         wd.fill(pool.data_ptr(), pool_len, seed)
         torch.cuda.synchronize()
@@ -139,7 +141,8 @@ def test_plan_learned_choice_and_rejections(env):
     theta = mlp.pack(p).astype(np.float32)
     assert H.hicr_mlp_set_params(ctx, theta) == H.OK
     assert int(mlp.predict(theta.astype(np.float64), mlp.features(descs["size"]))[0]) == 9
-    rc, plan, _ = H.hicr_plan_create(ctx, d, H.make_sched(65536, 1, 2, H.SCHED_LEARNED))
+    rc, plan, _ = H.hicr_plan_create(ctx, d, H.make_sched(65536, 1, 2, H.SCHED_LEARNED),
+                                     H.PLAN_GRAPH)
     assert rc == H.OK, H.hicr_last_error(ctx)
     for k in range(2):
         seed = 5200 + k
@@ -158,6 +161,7 @@ def test_plan_learned_choice_and_rejections(env):
     bad = d.copy()
     bad["src_slot"][3] = 10**6
     assert H.hicr_plan_create(ctx, bad)[0] == H.EBADSLOT
+    assert H.hicr_plan_create(ctx, d, None, 2)[0] == H.EINVAL
     # an empty plan launches nothing
     rc, plan, _ = H.hicr_plan_create(ctx, d[:0])
     assert rc == H.OK
