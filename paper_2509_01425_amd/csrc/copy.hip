@@ -15,7 +15,7 @@
 //      per lane; the at most 15 bytes before the first and after the last
 //      aligned destination vector are copied byte by byte, so no store ever
 //      touches a byte outside the request;
-//   4. completion counting is a separate small kernel, count_kernel, queued
+//   4. completion counting is a separate small kernel (count.hip) queued
 //      behind the copy launches of a submission on the same stream: the
 //      kernel boundary makes every copied byte visible before any counter
 //      rises, so the copy kernel needs no per-workgroup release (an
@@ -167,70 +167,10 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
   }
 }
 
-// Raise sent (source) and received (destination) of every request's slots.
-// Workgroup g takes requests [4096 g, 4096 g + 4096).  Requests often share
-// slots (a halo exchange names 8 slots 28,160 times), and device atomics on
-// one address serialise, so the counts are summed per slot in an LDS table
-// first: a bucket holds one slot and a packed count (sent in bits 0..15,
-// received in 16..31 -- at most 4,096 requests per group); a slot whose
-// bucket another slot holds goes straight to device memory.  Slot ids are
-// below 2^20, never ~0u.
-__global__ __launch_bounds__(kCopyBlock) void count_kernel(const uint64_t *slots, uint64_t n,
-                                                           uint64_t *counters) {
-  constexpr uint32_t kBuckets = 2048;
-  constexpr uint32_t kPerGroup = 4096;
-  constexpr uint32_t kEmpty = 0xffffffffu;
-  __shared__ uint32_t key[kBuckets], cnt[kBuckets];
-  const uint32_t tid = threadIdx.x;
-  const uint64_t i0 = (uint64_t)blockIdx.x * kPerGroup;
-  const uint64_t i1 = i0 + kPerGroup < n ? i0 + kPerGroup : n;
-  for (uint32_t h = tid; h < kBuckets; h += kCopyBlock) {
-    key[h] = kEmpty;
-    cnt[h] = 0;
-  }
-  __syncthreads();
-  auto add = [&](uint32_t slot, uint32_t inc, uint64_t *direct) {
-    const uint32_t h = slot & (kBuckets - 1);
-    const uint32_t old = atomicCAS(&key[h], kEmpty, slot);
-    if (old == kEmpty || old == slot)
-      atomicAdd(&cnt[h], inc);
-    else
-      __hip_atomic_fetch_add(direct, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  };
-  for (uint64_t i = i0 + tid; i < i1; i += kCopyBlock) {
-    const uint64_t sp = slots[i];
-    const uint32_t dslot = (uint32_t)(sp & 0xffffffffull), sslot = (uint32_t)(sp >> 32);
-    add(sslot, 1u, &counters[2 * (uint64_t)sslot]);
-    add(dslot, 1u << 16, &counters[2 * (uint64_t)dslot + 1]);
-  }
-  __syncthreads();
-  for (uint32_t h = tid; h < kBuckets; h += kCopyBlock) {
-    const uint32_t k = key[h];
-    if (k == kEmpty) continue;
-    const uint32_t c = cnt[h];
-    if (c & 0xffffu)
-      __hip_atomic_fetch_add(&counters[2 * (uint64_t)k], (uint64_t)(c & 0xffffu),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (c >> 16)
-      __hip_atomic_fetch_add(&counters[2 * (uint64_t)k + 1], (uint64_t)(c >> 16),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
 hipError_t launch_copy(const DevBatch &b, DevSched s, const DevSched *sched_dev, uint32_t grid,
                        hipStream_t stream) {
   if (b.n > kMaxLdsDescs || grid == 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(kCopyBlock), 0, stream, b, s, sched_dev);
-  return hipGetLastError();
-}
-
-hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters,
-                        hipStream_t stream) {
-  if (n == 0) return hipSuccess;
-  const uint64_t groups = (n + 4095) / 4096;
-  if (groups > 0x7fffffffull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(count_kernel, dim3((uint32_t)groups), dim3(kCopyBlock), 0, stream, slots, n,
-                     counters);
   return hipGetLastError();
 }
 
