@@ -8,17 +8,17 @@
 namespace hicr {
 
 // Raise sent (source) and received (destination) of every request's slots.
-// Workgroup g takes requests [4096 g, 4096 g + 4096).  Requests often share
+// Workgroup g takes requests [1024 g, 1024 g + 1024).  Requests often share
 // slots (a halo exchange names 8 slots 28,160 times), and device atomics on
 // one address serialise, so the counts are summed per slot in an LDS table
 // first: a bucket holds one slot and a packed count (sent in bits 0..15,
-// received in 16..31 -- at most 4,096 requests per group); a slot whose
+// received in 16..31 -- at most 1,024 requests per group); a slot whose
 // bucket another slot holds goes straight to device memory.  Slot ids are
 // below 2^20, never ~0u.
 __global__ __launch_bounds__(kCopyBlock) void count_kernel(const uint64_t *slots, uint64_t n,
                                                            uint64_t *counters) {
   constexpr uint32_t kBuckets = 2048;
-  constexpr uint32_t kPerGroup = 4096;
+  constexpr uint32_t kPerGroup = 1024;  // requests per group: short serial chains
   constexpr uint32_t kEmpty = 0xffffffffu;
   __shared__ uint32_t key[kBuckets], cnt[kBuckets];
   const uint32_t tid = threadIdx.x;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kCopyBlock) void count_kernel(const uint64_t *slots
 hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters,
                         hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  const uint64_t groups = (n + 4095) / 4096;
+  const uint64_t groups = (n + 1023) / 1024;
   if (groups > 0x7fffffffull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(count_kernel, dim3((uint32_t)groups), dim3(kCopyBlock), 0, stream, slots, n,
                      counters);
