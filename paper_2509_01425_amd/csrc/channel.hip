@@ -18,9 +18,9 @@
 // producer waves (one stream each) or one consumer (all four waves).  Waits
 // poll with relaxed device-scope loads and take one acquire fence once the
 // condition holds (an acquire per poll would invalidate the L2 on every
-// spin).  Producers publish up to 8 messages per release; consumers take up
-// to 16 per release across all of a channel's rings, and copy each batch as
-// one index space of 16-byte vectors.  The host launches no more workgroups
+// spin).  Producers publish up to 16 messages per release (8 on a locking
+// ring); consumers take up to 16 per release across all of their rings, and
+// copy each batch as one index space of 16-byte vectors.  The host launches no more workgroups
 // than the device holds at once, and every wait gives up after a
 // no-progress time-out or on the abort word, so every wave exits.
 #include "chan.h"
@@ -191,12 +191,17 @@ __device__ void seg_copy(const Seg *sg, uint32_t nseg, uint64_t total_v, uint32_
   }
 }
 
-constexpr uint32_t kProdBatch = 8;   // messages a producer publishes at once
+// Messages a producer publishes at once: 16 on a ring of its own, 8 on a
+// locking MPSC ring, where a larger reservation keeps the other producers
+// waiting for room longer (measured: 16 gave +15% on the non-locking pump and
+// -5% on the locking one).
+constexpr uint32_t kProdBatch = 16;
+constexpr uint32_t kProdBatchLocking = 8;
 constexpr uint32_t kConsBatch = 16;  // messages a consumer takes at once
 
 // One producer wave drives one stream: it takes as many of its next messages
-// as the ring has room for (up to kProdBatch), copies them as one batch,
-// writes their entries and publishes them with one release.
+// as the ring has room for (up to kProdBatch, or kProdBatchLocking), copies
+// them as one batch, writes their entries and publishes them with one release.
 __device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane, Seg *sg) {
   const DevStream st = a.streams[sid];
   const DevRing r = a.rings[st.ring];
@@ -212,8 +217,8 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane, Seg
   w.progress();
   uint64_t m = 0;
   while (m < st.n_msgs) {
-    // sizes and offsets of the next kProdBatch messages, one per lane
-    const bool have = lane < kProdBatch && m + lane < st.n_msgs;
+    // sizes and offsets of the next messages of this batch, one per lane
+    const bool have = lane < (locking ? kProdBatchLocking : kProdBatch) && m + lane < st.n_msgs;
     const uint64_t sz = have ? a.msg_size[st.first_msg + m + lane] : 0;
     const uint64_t off = have ? a.msg_off[st.first_msg + m + lane] : 0;
     const uint64_t incl = wave_scan(sz, lane);
