@@ -16,6 +16,7 @@ namespace hicr {
 constexpr uint64_t kEntrySizeMask = (1ull << 48) - 1;
 constexpr uint32_t kMaxProducers = 64;
 constexpr int kPumpBlock = 256;
+constexpr uint32_t kMaxTeam = 16;  // consumer workgroups of one locking MPSC ring
 
 // One 128-byte line per writer so producer and consumer never share a line.
 struct alignas(128) CoordLine {
@@ -42,12 +43,20 @@ struct DevRing {
   uint64_t entries;  // device address of E u64
   uint64_t E;
   uint64_t coord;    // device address of a RingCoord
+  // locking MPSC rings in a pump: per-message records {absolute ring byte
+  // position, output address, message index} indexed by (message counter -
+  // base_m), written by the producer before it publishes
+  uint64_t side;
+  uint64_t base_m;   // the ring's message counter when the pump starts
+  uint64_t side_n;   // records in `side` (messages of this pump through the ring)
 };
 
 enum : uint32_t { kModeSpsc = 0, kModeMpscLock = 1, kModeMpscNoLock = 2 };
 
-// One consumer unit (one workgroup).  kModeMpscLock: the shared ring of a
-// locking MPSC channel, K producers told apart by the entry's producer tag.
+// One consumer unit (one workgroup).  kModeMpscLock: a member of the team
+// that consumes the shared ring of a locking MPSC channel (K producers told
+// apart by the entry's producer tag); the team shares a claim counter and a
+// round table (rounds[k] = end + 1 of round k once defined, 0 before).
 // kModeSpsc: n_rings independent rings, each with exactly one producer stream
 // (SPSC rings and non-locking MPSC sub-rings, possibly of different
 // channels); ring q belongs to stream stream_of_prod[prod_stream_base + q].
@@ -60,6 +69,8 @@ struct DevChannel {
   uint64_t trace_base;  // first trace slot (locking MPSC)
   uint32_t prod_stream_base;  // index into stream_of_prod: K entries
   uint32_t pad;
+  uint64_t claim;   // locking team: device address of the round claim counter
+  uint64_t rounds;  // locking team: device address of the round table
 };
 
 struct DevStream {

@@ -30,6 +30,10 @@ struct hicr_channel_s {
   RingCoord *coord_host = nullptr;  // host view (host endpoints)
   RingCoord *coord_dev = nullptr;   // device view
   bool broken = false;
+  // Device endpoints: messages every ring has carried in earlier pumps.
+  // Pumps on one channel never overlap and always drain their messages, so
+  // this is the ring's message counter when the next pump starts.
+  std::vector<uint64_t> dev_msgs;
   struct RingHost {
     uint64_t tm = 0, tb = 0;  // producer side: enqueued
     uint64_t hm = 0, hb = 0;  // consumer side: released
@@ -194,6 +198,7 @@ int hicr_channel_create(hicr_ctx c, const hicr_channel_cfg *cfg, hicr_channel *o
     e = hipMalloc(&d, bytes);
     if (e == hipSuccess) e = hipMemset(d, 0, bytes);
     ch->coord_dev = static_cast<RingCoord *>(d);
+    ch->dev_msgs.assign(rings, 0);
   }
   if (e != hipSuccess) {
     free_channel(ch);
@@ -391,24 +396,47 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
       trace_total += st[it->second].n_msgs;
     }
   }
-  uint32_t n_lock = 0;
   std::vector<uint32_t> indep;  // streams whose ring is consumed on its own
+  std::vector<uint64_t> chan_bytes(chans.size(), 0), chan_msgs(chans.size(), 0);
+  std::vector<uint32_t> lock_chans;
+  uint64_t all_bytes = 0;
   for (uint32_t k = 0; k < chans.size(); k++) {
-    if (chans[k]->cfg.mode == HICR_CH_MPSC_LOCK) {
-      n_lock++;
-      continue;
-    }
     for (uint32_t p = 0; p < chans[k]->cfg.producers; p++) {
       auto it = prod_stream.find(std::make_pair(chans[k], p));
-      if (it != prod_stream.end()) indep.push_back(it->second);
+      if (it == prod_stream.end()) continue;
+      chan_bytes[k] += stream_bytes[it->second];
+      chan_msgs[k] += st[it->second].n_msgs;
+      if (chans[k]->cfg.mode != HICR_CH_MPSC_LOCK) indep.push_back(it->second);
     }
+    all_bytes += chan_bytes[k];
+    if (chans[k]->cfg.mode == HICR_CH_MPSC_LOCK) lock_chans.push_back(k);
   }
   const uint64_t min_units = (indep.size() + kMaxProducers - 1) / kMaxProducers;
-  if ((uint64_t)prod_wgs + n_lock + min_units > cap)
+  if ((uint64_t)prod_wgs + lock_chans.size() + min_units > cap)
     return fail(c, HICR_EINVAL, "%llu workgroups do not fit the device at once (%d x %d)",
-                (unsigned long long)(prod_wgs + n_lock + min_units), c->n_cu, c->pump_occ);
+                (unsigned long long)(prod_wgs + lock_chans.size() + min_units), c->n_cu,
+                c->pump_occ);
+  // A locking MPSC ring is drained by a team sized to its share of the bytes
+  // (every consumer workgroup should carry about the same), at most
+  // kMaxTeam, and trimmed while the single-producer rings would not fit.
+  const uint64_t budget = cap - prod_wgs;
+  const uint64_t per_unit = std::max<uint64_t>(1, all_bytes / std::max<uint64_t>(1, budget));
+  std::map<uint32_t, uint32_t> team;
+  uint64_t team_total = 0;
+  for (uint32_t k : lock_chans) {
+    const uint64_t t = std::min<uint64_t>(kMaxTeam, std::max<uint64_t>(1, (chan_bytes[k] + per_unit - 1) / per_unit));
+    team[k] = (uint32_t)t;
+    team_total += t;
+  }
+  while (team_total + min_units > budget) {
+    uint32_t big = lock_chans[0];
+    for (uint32_t k : lock_chans)
+      if (team[k] > team[big]) big = k;
+    team[big]--;  // the fit check above guarantees one member per channel fits
+    team_total--;
+  }
   const uint32_t n_indep_units =
-      (uint32_t)std::min<uint64_t>(indep.size(), cap - prod_wgs - n_lock);
+      (uint32_t)std::min<uint64_t>(indep.size(), budget - team_total);
   // longest first onto the least loaded unit (at most kMaxProducers rings each)
   std::vector<std::vector<uint32_t>> unit_streams(n_indep_units);
   {
@@ -432,6 +460,20 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   std::vector<uint32_t> sop;
   std::vector<DevStream> ds(n);
   std::vector<uint32_t> unit_of(n, 0), ring_of(n, 0);
+  // device scratch of the locking teams: per channel a claim counter, a round
+  // table (zeroed) and one 24-byte record per message
+  std::vector<uint64_t> lock_claim_off, lock_side_off;
+  uint64_t team_bytes = 0;
+  for (uint32_t k : lock_chans) {
+    lock_claim_off.push_back(team_bytes);
+    team_bytes += 8 * (1 + chan_msgs[k] + team[k] + 1);
+  }
+  const uint64_t team_zero_bytes = team_bytes;
+  for (uint32_t k : lock_chans) {
+    lock_side_off.push_back(team_bytes);
+    team_bytes += 24 * chan_msgs[k];
+  }
+  std::vector<uint32_t> lock_unit_first;  // first unit of each locking team
   for (uint32_t k = 0; k < chans.size(); k++) {
     hicr_channel ch = chans[k];
     if (ch->cfg.mode != HICR_CH_MPSC_LOCK) continue;
@@ -442,7 +484,9 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
     d.K = ch->cfg.producers;
     d.trace_base = chan_trace[k];
     d.prod_stream_base = (uint32_t)sop.size();
-    rings.push_back(dev_ring(ch, 0));
+    DevRing rg = dev_ring(ch, 0);
+    rg.base_m = ch->dev_msgs[0];
+    rings.push_back(rg);
     uint32_t any = 0;
     for (uint32_t p = 0; p < d.K; p++) {
       auto it = prod_stream.find(std::make_pair(ch, p));
@@ -457,7 +501,8 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
         d.total_msgs += st[it->second].n_msgs;
       }
     }
-    dch.push_back(d);
+    lock_unit_first.push_back((uint32_t)dch.size());
+    for (uint32_t m = 0; m < team[k]; m++) dch.push_back(d);  // claim/rounds set below
   }
   for (const auto &us : unit_streams) {
     DevChannel d{};
@@ -505,21 +550,36 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
     roles.push_back(r);
   }
   for (uint32_t k = 0; k < nch; k++) roles.push_back(DevRole{1, 1, {k, 0, 0, 0}});
-  // one upload: [err words | rings | channels | streams | sop | roles | msg_off | msg_size]
+  // one upload: [err words | rings | channels | streams | sop | roles | msg_off | msg_size],
+  // then the locking teams' device scratch (not uploaded; its head is zeroed)
   auto align = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
   uint64_t o_err = 0, o_ring = 256, o_ch = align(o_ring + rings.size() * sizeof(DevRing)),
            o_st = align(o_ch + dch.size() * sizeof(DevChannel)),
            o_sop = align(o_st + ds.size() * sizeof(DevStream)),
            o_role = align(o_sop + sop.size() * 4), o_off = align(o_role + roles.size() * sizeof(DevRole)),
-           o_size = align(o_off + n_msgs * 8), total = align(o_size + n_msgs * 8);
+           o_size = align(o_off + n_msgs * 8), upload = align(o_size + n_msgs * 8),
+           o_team = upload, total = align(o_team + team_bytes);
   Extra x;
   x.pump = true;
-  hipError_t e = hipHostMalloc(&x.h_buf, total, hipHostMallocDefault);
-  if (e != hipSuccess) return fail(c, HICR_ENOMEM, "pump staging (%llu bytes)", (unsigned long long)total);
+  hipError_t e = hipHostMalloc(&x.h_buf, upload, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(c, HICR_ENOMEM, "pump staging (%llu bytes)", (unsigned long long)upload);
   e = hipMalloc(&x.d_buf, total);
   if (e != hipSuccess) {
     (void)hipHostFree(x.h_buf);
     return fail(c, HICR_ENOMEM, "pump tables (%llu bytes)", (unsigned long long)total);
+  }
+  {
+    // addresses of the locking teams' scratch, now that the buffer exists
+    const uint64_t dbase = reinterpret_cast<uint64_t>(x.d_buf) + o_team;
+    for (size_t t = 0; t < lock_chans.size(); t++) {
+      const uint32_t u0 = lock_unit_first[t];
+      rings[dch[u0].first_ring].side = dbase + lock_side_off[t];
+      rings[dch[u0].first_ring].side_n = chan_msgs[lock_chans[t]];
+      for (uint32_t m = 0; m < team[lock_chans[t]]; m++) {
+        dch[u0 + m].claim = dbase + lock_claim_off[t];
+        dch[u0 + m].rounds = dbase + lock_claim_off[t] + 8;
+      }
+    }
   }
   char *h = static_cast<char *>(x.h_buf);
   std::memset(h, 0, 256);
@@ -547,7 +607,8 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   a.err = reinterpret_cast<uint32_t *>(d + o_err);
   const uint64_t tns = timeout_ns ? timeout_ns : 10'000'000'000ull;
   a.timeout_ticks = tns / 10;  // 100 MHz device clock
-  e = hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, s);
+  e = hipMemcpyAsync(d, h, upload, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && team_zero_bytes) e = hipMemsetAsync(d + o_team, 0, team_zero_bytes, s);
   if (e == hipSuccess) e = launch_pump(a, n_wgs, s);
   // error words come back into the (no longer needed) head of the staging
   if (e == hipSuccess) e = hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, s);
@@ -562,6 +623,12 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   }
   x.abort_word = a.err + 1;
   x.chans = chans;
+  // the rings' message counters when the next pump starts
+  for (uint32_t i = 0; i < n; i++) {
+    hicr_channel ch = st[i].channel;
+    const uint32_t r = ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? st[i].producer : 0;
+    ch->dev_msgs[r] += st[i].n_msgs;
+  }
   {
     std::lock_guard<std::mutex> ga(c->abort_mu);
     c->abort_words.push_back(x.abort_word);

@@ -202,7 +202,10 @@ constexpr uint32_t kConsBatch = 16;  // messages a consumer takes at once
 // One producer wave drives one stream: it takes as many of its next messages
 // as the ring has room for (up to kProdBatch, or kProdBatchLocking), copies
 // them as one batch, writes their entries and publishes them with one release.
-__device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane, Seg *sg) {
+__device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, Seg *sg) {
+  // the stream id is the same in every lane of the wave; saying so lets the
+  // stream and ring descriptors live in scalar registers
+  const uint32_t sid = __builtin_amdgcn_readfirstlane(sid_in);
   const DevStream st = a.streams[sid];
   const DevRing r = a.rings[st.ring];
   const bool locking = a.chans[st.channel].mode == kModeMpscLock;
@@ -216,6 +219,7 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane, Seg
   Watch w{0, a.timeout_ticks, a.err};
   w.progress();
   uint64_t m = 0;
+  uint64_t out_run = 0;  // output bytes of this stream's earlier messages
   while (m < st.n_msgs) {
     // sizes and offsets of the next messages of this batch, one per lane
     const bool have = lane < (locking ? kProdBatchLocking : kProdBatch) && m + lane < st.n_msgs;
@@ -257,6 +261,27 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane, Seg
       st_rlx(rb_a, my_tb + bytes);
       st_rel(sv_a, ticket + 1);
     }
+    // entries (and, on a locking ring, the records the consumer team reads)
+    // are written now, before the copy, so sizes and offsets need not stay
+    // in registers across it; the release before publication covers them
+    if (lane < j) {
+      *(GLOBAL uint64_t *)(r.entries + 8 * ((my_tm + lane) % r.E)) =
+          sz | ((uint64_t)st.producer << 48);
+      if (locking) {
+        // the message's record for the consumer team: ring byte position,
+        // output address, message index (a counter outside this pump's
+        // records means the ring's state is not what the host planned for)
+        const uint64_t idx = my_tm + lane - r.base_m;
+        if (idx < r.side_n) {
+          uint64_t *rec = (uint64_t *)(r.side + 24 * idx);
+          rec[0] = my_tb + incl - sz;
+          rec[1] = st.out_base + out_run + incl - sz;
+          rec[2] = st.first_msg + m + lane;
+        } else {
+          __hip_atomic_fetch_or(&a.err[0], kErrCorrupt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
     // segments: message l of the batch -> ring bytes at (my_tb + excl_l) mod P
     if (lane < j) {
       const uint64_t pos = (my_tb + incl - sz) % r.P;
@@ -271,9 +296,6 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane, Seg
     const uint64_t total_v = shfl64(nv_incl, 63);
     wave_sync();
     seg_copy<64, 2>(sg, 2 * j, total_v, lane);
-    if (lane < j)
-      *(GLOBAL uint64_t *)(r.entries + 8 * ((my_tm + lane) % r.E)) =
-          sz | ((uint64_t)st.producer << 48);
     if (locking) {
       // publish in reservation order, carrying the predecessors' writes
       while (ld_rlx(tm_a) != my_tm) {
@@ -290,6 +312,7 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid, uint32_t lane, Seg
     tm = my_tm + j;
     tb = my_tb + bytes;
     m += j;
+    out_run += bytes;
     w.progress();
   }
 }
@@ -464,15 +487,163 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
   __threadfence();
 }
 
+// A locking MPSC ring consumed by a team of workgroups.  The ring holds one
+// total order; it is cut into rounds of consecutive messages.  A member
+// claims the next round number; once the previous round is defined the new
+// round starts where that one ends and takes up to kConsBatch messages that
+// are already published (so a round never waits on room the ring cannot
+// give); the member copies it and releases the ring room in round order.
+// Each message's ring position and output address come from the record its
+// producer wrote before publishing, so a member never needs another round's
+// entries (which producers may already be reusing).
+__device__ void run_lock_team(const PumpArgs &a, uint32_t uid, uint32_t tid) {
+  __shared__ uint64_t s_pout[kMaxProducers], s_pbytes[kMaxProducers];
+  __shared__ uint64_t s_pfirst[kMaxProducers], s_pn[kMaxProducers];
+  __shared__ uint32_t s_psid[kMaxProducers];
+  __shared__ uint64_t s_sz[kConsBatch], s_pos[kConsBatch], s_out[kConsBatch];
+  __shared__ uint32_t s_p[kConsBatch], s_bad;
+  __shared__ Seg s_seg[2 * kConsBatch];
+  __shared__ uint64_t s_start, s_end, s_total_v, s_bend;
+  __shared__ uint32_t s_stop, s_nseg;
+  const DevChannel u = a.chans[uid];
+  const DevRing r = a.rings[u.first_ring];
+  const uint64_t tm_a = r.coord + offsetof(RingCoord, prod);
+  const uint64_t hm_a = r.coord + offsetof(RingCoord, cons), hb_a = hm_a + 8;
+  const uint64_t last = r.base_m + u.total_msgs;  // counter after this pump's messages
+  uint64_t *rounds = (uint64_t *)u.rounds;
+  for (uint32_t p = tid; p < u.K; p += kPumpBlock) {
+    const uint32_t sid = a.stream_of_prod[u.prod_stream_base + p];
+    const DevStream so = a.streams[sid];
+    s_psid[p] = sid;
+    s_pout[p] = so.out_base;
+    s_pbytes[p] = so.out_bytes;
+    s_pfirst[p] = so.first_msg;
+    s_pn[p] = so.n_msgs;
+  }
+  Watch w{0, a.timeout_ticks, a.err};
+  w.progress();
+  for (;;) {
+    if (tid == 0) {
+      uint32_t stop = 0;
+      const uint64_t k = __hip_atomic_fetch_add((uint64_t *)u.claim, 1ull, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t start = r.base_m;
+      if (k > 0) {
+        uint64_t v;
+        while ((v = ld_rlx((uint64_t)&rounds[k - 1])) == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          if (w.expired()) {
+            stop = 1;
+            break;
+          }
+        }
+        start = v - 1;
+      }
+      uint64_t end = start;
+      if (!stop && start < last) {
+        uint64_t tm;
+        while ((tm = ld_rlx(tm_a)) <= start) {
+          __builtin_amdgcn_s_sleep(2);
+          if (w.expired()) {
+            stop = 1;
+            break;
+          }
+        }
+        if (!stop) {
+          end = start + kConsBatch;
+          if (end > tm) end = tm;
+          if (end > last) end = last;
+        }
+      }
+      // round k is defined even when empty: later claimers see where it ends
+      if (!stop) st_rlx((uint64_t)&rounds[k], end + 1);
+      s_start = start;
+      s_end = end;
+      s_stop = stop || start >= last;
+      s_bad = 0;
+    }
+    __syncthreads();
+    if (s_stop) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // records and payload of the round
+    const uint64_t start = s_start, n = s_end - s_start;
+    if (tid < n) {
+      const uint64_t seq = start + tid;
+      const uint64_t e = *(const GLOBAL uint64_t *)(r.entries + 8 * (seq % r.E));
+      const uint64_t *rec = (const uint64_t *)(r.side + 24 * (seq - r.base_m));
+      const uint64_t sz = e & kEntrySizeMask, pos = rec[0], out = rec[1], mi = rec[2];
+      const uint32_t p = (uint32_t)(e >> 48) % u.K;
+      // checked against the producer's stream before any byte moves
+      if (sz > r.P || out < s_pout[p] || out - s_pout[p] > s_pbytes[p] ||
+          sz > s_pbytes[p] - (out - s_pout[p]) || mi < s_pfirst[p] || mi - s_pfirst[p] >= s_pn[p])
+        atomicOr(&s_bad, 1u);
+      s_sz[tid] = sz;
+      s_pos[tid] = pos;
+      s_out[tid] = out;
+      s_p[tid] = p;
+      if (a.trace) a.trace[u.trace_base + (seq - r.base_m)] = s_psid[p];
+      if (a.ts_pop) a.ts_pop[mi] = wall_clock64();
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t nseg = 0;
+      uint64_t v = 0;
+      for (uint32_t i = 0; i < n; i++) {
+        const uint64_t sz = s_sz[i], pos = s_pos[i] % r.P;
+        const uint64_t first = r.P - pos < sz ? r.P - pos : sz;
+        s_seg[nseg] = make_seg(s_out[i], r.payload + pos, first);
+        s_seg[nseg].v0 = v;
+        v += s_seg[nseg++].nv;
+        if (sz > first) {
+          s_seg[nseg] = make_seg(s_out[i] + first, r.payload, sz - first);
+          s_seg[nseg].v0 = v;
+          v += s_seg[nseg++].nv;
+        }
+      }
+      s_nseg = nseg;
+      s_total_v = v;
+      s_bend = n ? s_pos[n - 1] + s_sz[n - 1] : 0;
+      if (s_bad) {
+        __hip_atomic_fetch_or(&a.err[0], kErrCorrupt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_stop = 1;
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    seg_copy<kPumpBlock, 4>(s_seg, s_nseg, s_total_v, tid);
+    __syncthreads();  // every read of the ring has completed
+    if (tid == 0) {
+      // release in round order
+      while (ld_rlx(hm_a) != start) {
+        __builtin_amdgcn_s_sleep(1);
+        if (w.expired()) {
+          s_stop = 1;
+          break;
+        }
+      }
+      if (!s_stop) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        st_rlx(hb_a, s_bend);
+        st_rlx(hm_a, s_end);
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    w.progress();
+  }
+  __threadfence();
+}
+
 __global__ __launch_bounds__(kPumpBlock) __attribute__((amdgpu_waves_per_eu(6, 8)))
 void pump_kernel(PumpArgs a) {
   const DevRole role = a.roles[blockIdx.x];
   const uint32_t tid = threadIdx.x;
   __shared__ Seg s_pseg[4][2 * kProdBatch];
   if (role.kind == 0) {
-    const uint32_t wave = tid >> 6;
-    if (wave < role.count) run_producer(a, role.ids[wave], tid & 63, s_pseg[wave]);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
+    if (wave < role.count) run_producer(a, a.roles[blockIdx.x].ids[wave], tid & 63, s_pseg[wave]);
     __threadfence();
+  } else if (a.chans[role.ids[0]].mode == kModeMpscLock) {
+    run_lock_team(a, role.ids[0], tid);
   } else {
     run_consumer(a, role.ids[0], tid);
   }
