@@ -217,6 +217,9 @@ int hicr_autotune(hicr_ctx ctx, const hicr_desc *descs, uint64_t n, uint32_t rep
  * schedule is used. */
 int hicr_tune_add(hicr_ctx ctx, const hicr_desc *descs, uint64_t n, uint32_t cls);
 int hicr_tune_clear(hicr_ctx ctx);
+/* The class HICR_SCHED_TUNED would give this batch (ties: the earliest
+ * entry); an empty table -> HICR_EINVAL. */
+int hicr_tune_lookup(hicr_ctx ctx, const hicr_desc *descs, uint64_t n, uint32_t *cls);
 
 /* The schedule network, 32 -> 64 -> 64 -> 12 with ReLU, fp32, parameters in
  * the flat layout W1[64][32] b1[64] W2[64][64] b2[64] W3[12][64] b3[12]
@@ -374,11 +377,12 @@ typedef struct {
 } hicr_pump_io;
 
 /* Run every stream through its device-endpoint channel in one persistent
- * launch on `stream`: one GPU wave per producer stream; one consumer
- * workgroup per locking MPSC channel (its shared ring), and the rings that
- * have a single producer (SPSC rings, non-locking MPSC sub-rings) spread over
- * the remaining workgroups the device holds, balanced by bytes -- the
- * consumer of a non-locking MPSC channel is such a team.  Validated on the host (slots, ranges, sizes, one stream per
+ * launch on `stream`: one GPU wave per producer stream.  The consumer side
+ * of each channel is a team of workgroups: a locking MPSC channel's shared
+ * ring is drained in its total order by up to 16 workgroups that take turns
+ * (rounds of consecutive messages, ring room released in order); the rings
+ * with a single producer (SPSC rings, non-locking MPSC sub-rings) are spread
+ * over the remaining workgroups the device holds, balanced by bytes.  Validated on the host (slots, ranges, sizes, one stream per
  * (channel, producer)); HICR_EINVAL if the launch would not fit on the device
  * at once.  Asynchronous; hicr_fence reports a time-out or abort.  A channel
  * has one producer and one consumer per ring: two pump launches that drive
@@ -388,6 +392,24 @@ int hicr_channel_pump(hicr_ctx ctx, const hicr_stream *streams, uint32_t n_strea
                       const hicr_pump_io *io, void *stream);
 /* Ask running pumps of this context to stop (they end at their next wait). */
 int hicr_channel_abort(hicr_ctx ctx);
+
+/* Device view of one ring, for producers and consumers written in the
+ * caller's own kernels with hicr_device.h (device addresses). */
+typedef struct {
+  uint64_t payload;  /* P payload bytes */
+  uint64_t P;
+  uint64_t entries;  /* E u64 entries: size | producer << 48 */
+  uint64_t E;
+  uint64_t coord;    /* the ring's coordination block (library memory) */
+  uint32_t producer; /* tag a producer writes into this ring's entries */
+  uint32_t pad;
+} hicr_dev_ring;
+/* Ring `ring` of a device-endpoint SPSC (ring 0) or non-locking MPSC (ring =
+ * producer) channel.  Host-endpoint channels and bad ring numbers ->
+ * HICR_EINVAL; locking MPSC -> HICR_EUNSUPPORTED (its producers take a lock
+ * that only the pump implements).  From then on the channel belongs to user
+ * kernels: hicr_channel_pump refuses it (HICR_EINVAL). */
+int hicr_channel_device_view(hicr_channel ch, uint32_t ring, hicr_dev_ring *out);
 
 /* ---------------------------------------------------- ping-pong (growth) */
 /* Sec. 5, Test Case 1 on one GPU: a pinger and a ponger, each a group of W

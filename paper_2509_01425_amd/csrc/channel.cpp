@@ -34,6 +34,7 @@ struct hicr_channel_s {
   // Pumps on one channel never overlap and always drain their messages, so
   // this is the ring's message counter when the next pump starts.
   std::vector<uint64_t> dev_msgs;
+  bool user_kernels = false;  // handed to caller kernels (hicr_device.h)
   struct RingHost {
     uint64_t tm = 0, tb = 0;  // producer side: enqueued
     uint64_t hm = 0, hb = 0;  // consumer side: released
@@ -347,6 +348,8 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
     if (ch->cfg.endpoints != HICR_CH_DEVICE)
       return fail(c, HICR_EINVAL, "stream %u: channel has host endpoints", i);
     if (ch->broken) return fail(c, HICR_EINVAL, "stream %u: channel broken by an earlier error", i);
+    if (ch->user_kernels)
+      return fail(c, HICR_EINVAL, "stream %u: channel belongs to user kernels", i);
     if (st[i].producer >= ch->cfg.producers) return fail(c, HICR_EINVAL, "stream %u: producer", i);
     if (!prod_stream.emplace(std::make_pair(ch, st[i].producer), i).second)
       return fail(c, HICR_EINVAL, "stream %u: producer already has a stream", i);
@@ -693,6 +696,28 @@ int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_
                        stream ? static_cast<hipStream_t>(stream) : c->stream, &x);
   if (rc == HICR_OK && x.ev) c->extra.push_back(x);
   return rc;
+}
+
+int hicr_channel_device_view(hicr_channel ch, uint32_t ring, hicr_dev_ring *out) {
+  if (!ch || !out) return HICR_EINVAL;
+  hicr_ctx c = ch->ctx;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!registered(c, ch)) return HICR_EINVAL;
+  if (ch->cfg.endpoints != HICR_CH_DEVICE) return fail(c, HICR_EINVAL, "host-endpoint channel");
+  if (ch->cfg.mode == HICR_CH_MPSC_LOCK)
+    return fail(c, HICR_EUNSUPPORTED, "locking MPSC rings are driven by the pump only");
+  if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
+  if (ch->broken) return fail(c, HICR_EINVAL, "channel broken by an earlier error");
+  const DevRing r = dev_ring(ch, ring);
+  out->payload = r.payload;
+  out->P = r.P;
+  out->entries = r.entries;
+  out->E = r.E;
+  out->coord = r.coord;
+  out->producer = ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? ring : 0;
+  out->pad = 0;
+  ch->user_kernels = true;
+  return HICR_OK;
 }
 
 int hicr_channel_abort(hicr_ctx c) {

@@ -307,7 +307,12 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, 
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     if (a.ts_push && lane < j) a.ts_push[st.first_msg + m + lane] = wall_clock64();
-    if (lane == 0) st_rlx(tm_a, my_tm + j);
+    if (lane == 0) {
+      // a ring of its own also publishes its byte counter, the form user
+      // kernels (hicr_device.h) resume from
+      if (!locking) st_rlx(tm_a + 8, my_tb + bytes);
+      st_rlx(tm_a, my_tm + j);
+    }
     wave_sync();
     tm = my_tm + j;
     tb = my_tb + bytes;

@@ -87,15 +87,23 @@ static int ensure_act(hicr_ctx c, SchedState *s, int B) {
 }
 
 static uint32_t nearest(const SchedState *s, const float *f) {
+  // exact squared distances; a candidate is dropped as soon as a partial sum
+  // (8 bins at a time) already exceeds the best one, which skips most of the
+  // table without changing the answer (first minimum wins, as in a full scan)
   uint32_t best = 0;
   float bd = 3.4e38f;
   for (size_t k = 0; k < s->feats.size(); k++) {
+    const float *g = s->feats[k].data();
     float d = 0.f;
-    for (int b = 0; b < kMlpIn; b++) {
-      const float x = s->feats[k][b] - f[b];
-      d += x * x;
+    int b = 0;
+    for (; b < kMlpIn; b += 8) {
+      for (int q = b; q < b + 8; q++) {
+        const float x = g[q] - f[q];
+        d += x * x;
+      }
+      if (d >= bd) break;
     }
-    if (d < bd) {
+    if (b >= kMlpIn && d < bd) {
       bd = d;
       best = s->cls[k];
     }
@@ -263,6 +271,16 @@ int hicr_tune_add(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t cls) 
   if (n) batch_features(&descs[0].size, n, sizeof(hicr_desc), f.data());
   s->feats.push_back(f);
   s->cls.push_back(cls);
+  return HICR_OK;
+}
+
+int hicr_tune_lookup(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t *cls) {
+  if (!c || (n && !descs) || !cls) return HICR_EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->sched || c->sched->feats.empty()) return fail(c, HICR_EINVAL, "empty tuned table");
+  std::array<float, kMlpIn> f{};
+  if (n) batch_features(&descs[0].size, n, sizeof(hicr_desc), f.data());
+  *cls = nearest(c->sched, f.data());
   return HICR_OK;
 }
 

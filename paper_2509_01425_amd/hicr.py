@@ -104,6 +104,12 @@ class hicr_serve_stats(ctypes.Structure):
                 ("max_inflight_requests", ctypes.c_uint64), ("wall_ns", ctypes.c_uint64)]
 
 
+class hicr_dev_ring(ctypes.Structure):
+    _fields_ = [("payload", ctypes.c_uint64), ("P", ctypes.c_uint64), ("entries", ctypes.c_uint64),
+                ("E", ctypes.c_uint64), ("coord", ctypes.c_uint64), ("producer", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
 class hicr_dobj_handle(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("size", ctypes.c_uint64), ("offset", ctypes.c_uint64),
                 ("slot", ctypes.c_uint32), ("memspace", ctypes.c_uint32)]
@@ -144,10 +150,12 @@ _SIGNATURES = {
     "hicr_channel_pump": (_int, [_vp, ctypes.POINTER(hicr_stream), _u32,
                                  ctypes.POINTER(hicr_pump_io), _vp]),
     "hicr_channel_abort": (_int, [_vp]),
+    "hicr_channel_device_view": (_int, [_vp, _u32, ctypes.POINTER(hicr_dev_ring)]),
     "hicr_sched_features": (_int, [_vp, _u64, _vp]),
     "hicr_autotune": (_int, [_vp, _vp, _u64, _u32, _vp, _pu32]),
     "hicr_tune_add": (_int, [_vp, _vp, _u64, _u32]),
     "hicr_tune_clear": (_int, [_vp]),
+    "hicr_tune_lookup": (_int, [_vp, _vp, _u64, _pu32]),
     "hicr_mlp_set_params": (_int, [_vp, _vp]),
     "hicr_mlp_get_params": (_int, [_vp, _vp]),
     "hicr_mlp_forward": (_int, [_vp, _vp, _u32, _vp]),
@@ -323,6 +331,12 @@ def hicr_channel_create(ctx, cfg: hicr_channel_cfg):
     return rc, out.value
 
 
+def hicr_channel_device_view(ch, ring: int = 0):
+    v = hicr_dev_ring()
+    rc = lib().hicr_channel_device_view(ch, ring, ctypes.byref(v))
+    return rc, v
+
+
 def hicr_channel_destroy(ch) -> int:
     return lib().hicr_channel_destroy(ch)
 
@@ -388,6 +402,13 @@ def hicr_autotune(ctx, descs: np.ndarray, reps: int = 3):
     rc = lib().hicr_autotune(ctx, d.ctypes.data if d.size else None, d.size, reps,
                              times.ctypes.data, ctypes.byref(best))
     return rc, times, best.value
+
+
+def hicr_tune_lookup(ctx, descs: np.ndarray):
+    d = _descs(descs)
+    out = _u32(0)
+    rc = lib().hicr_tune_lookup(ctx, d.ctypes.data if d.size else None, d.size, ctypes.byref(out))
+    return rc, out.value
 
 
 def hicr_tune_add(ctx, descs: np.ndarray, cls: int) -> int:

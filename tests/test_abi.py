@@ -75,7 +75,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     structs = {"hicr_sched": H.hicr_sched, "hicr_channel_cfg": H.hicr_channel_cfg,
                "hicr_stream": H.hicr_stream, "hicr_pump_io": H.hicr_pump_io,
                "hicr_request": H.hicr_request, "hicr_serve_cfg": H.hicr_serve_cfg,
-               "hicr_serve_stats": H.hicr_serve_stats, "hicr_dobj_handle": H.hicr_dobj_handle}
+               "hicr_serve_stats": H.hicr_serve_stats, "hicr_dobj_handle": H.hicr_dobj_handle,
+               "hicr_dev_ring": H.hicr_dev_ring}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hicr.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} sizeof %zu\\n", sizeof({name}));')

@@ -186,3 +186,29 @@ def test_learned_submission_picks_oracle_class_and_moves_bytes(env):
         assert H.hicr_slot_deregister(ctx, int(s)) == H.OK
 
 
+
+
+def test_tuned_table_lookup_is_the_nearest_feature(env):
+    """The tuned table's choice equals a brute-force nearest neighbour over
+    the oracle's features (first minimum on ties); an empty table is an
+    error."""
+    torch, H, ctx = env
+    assert H.hicr_tune_clear(ctx) == H.OK
+    assert H.hicr_tune_lookup(ctx, wm.family(0)[0])[0] == H.EINVAL
+    table = [wm.family(b)[0] for b in range(300)]
+    g = np.random.default_rng(4)
+    labels = g.integers(0, 12, size=len(table))
+    for d, c in zip(table, labels):
+        assert H.hicr_tune_add(ctx, d, int(c)) == H.OK
+    feats = np.array([mlp.features(d["size"]) for d in table])
+    for b in range(300, 420):
+        d = wm.family(b)[0]
+        dist = ((feats - mlp.features(d["size"])[None, :]) ** 2).sum(1)
+        # the library sums in fp32: any entry within rounding of the minimum
+        # may win; otherwise the choice is unique
+        near = dist <= dist.min() + 1e-4 * max(1.0, dist.min())
+        rc, got = H.hicr_tune_lookup(ctx, d)
+        assert rc == H.OK and got in set(int(x) for x in labels[near]), b
+        if near.sum() == 1:
+            assert got == int(labels[int(np.argmin(dist))])
+    assert H.hicr_tune_clear(ctx) == H.OK
