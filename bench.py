@@ -614,11 +614,26 @@ def main():
     per_launch = np.array(moved[args.warmup:], dtype=np.float64)
     achieved = float(np.mean(per_launch / (kern_ms * 1e-3)) / 1e9)
     traffic = traffic_per_launch()
+    # a plain aligned 16-byte copy of 4 GiB inside the same pool, as the
+    # practical ceiling of a read+write stream on this machine (context only)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cn = 4 << 30
+    wd.ref_copy(pool.data_ptr() + cn, pool.data_ptr(), cn, 1024, stream.cuda_stream)
+    ce_ms = []
+    for _ in range(3):
+        ce0.record(stream)
+        wd.ref_copy(pool.data_ptr() + cn, pool.data_ptr(), cn, 1024, stream.cuda_stream)
+        ce1.record(stream)
+        ce1.synchronize()
+        ce_ms.append(ce0.elapsed_time(ce1))
+    ceiling = 2 * cn / (float(np.median(ce_ms)) * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
             "kernel": "hicr::copy_kernel", "avg_launch_ms": round(float(kern_ms.mean()), 4),
-            "algorithmic_bytes_per_launch": int(per_launch.mean())}
+            "algorithmic_bytes_per_launch": int(per_launch.mean()),
+            "plain_copy_ceiling": round(ceiling, 1),
+            "frac_of_plain_copy": round(achieved / ceiling, 4)}
     out = {
         "metric": METRIC, "value": round(timed_bytes / total / 1e9, 1), "unit": "GB/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -87,16 +87,26 @@ __device__ __forceinline__ void ring_put(const DevRing &r, uint64_t pos, uint64_
 }
 
 // No-progress watchdog for spin waits.
+// The error and abort words are shared by every wave of the pump, so a wave
+// looks at them at most once per kWatchTicks of its own waiting (10 us of the
+// 100 MHz clock) instead of on every poll: thousands of spinning waves
+// reading one address would otherwise queue at one memory channel.
+constexpr uint64_t kWatchTicks = 1000;
+
 struct Watch {
   uint64_t deadline, span;
   uint32_t *err;
+  uint64_t next;
   __device__ void progress() { deadline = wall_clock64() + span; }
   // true when the wait must stop (time-out recorded, or abort requested)
   __device__ bool expired() {
+    const uint64_t now = wall_clock64();
+    if (now < next) return false;
+    next = now + kWatchTicks;
     if (__hip_atomic_load(&err[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
         __hip_atomic_load(&err[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return true;
-    if (wall_clock64() > deadline) {
+    if (now > deadline) {
       __hip_atomic_fetch_or(&err[0], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return true;
     }
@@ -216,7 +226,7 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, 
   // rings are empty when a pump starts: the producer side resumes at the
   // consumer's released counters
   uint64_t tm = ld_acq(tm_a), tb = ld_acq(hb_a);
-  Watch w{0, a.timeout_ticks, a.err};
+  Watch w{0, a.timeout_ticks, a.err, 0};
   w.progress();
   uint64_t m = 0;
   uint64_t out_run = 0;  // output bytes of this stream's earlier messages
@@ -371,7 +381,7 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
     s_cnt[p] = 0;
   }
   __syncthreads();
-  Watch w{0, a.timeout_ticks, a.err};
+  Watch w{0, a.timeout_ticks, a.err, 0};
   w.progress();
   uint64_t done = 0;
   uint32_t rr = 0;
@@ -525,7 +535,7 @@ __device__ void run_lock_team(const PumpArgs &a, uint32_t uid, uint32_t tid) {
     s_pfirst[p] = so.first_msg;
     s_pn[p] = so.n_msgs;
   }
-  Watch w{0, a.timeout_ticks, a.err};
+  Watch w{0, a.timeout_ticks, a.err, 0};
   w.progress();
   for (;;) {
     if (tid == 0) {

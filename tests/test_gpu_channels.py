@@ -357,3 +357,68 @@ def test_pump_full_size_sampled(env, mode):
         assert H.hicr_channel_destroy(ch) == H.OK
     del rig
     torch.cuda.empty_cache()
+
+
+def _blocking_rig(torch, H, wd, ctx, n_msgs, msg_bytes, P, E, locking=False):
+    """A device channel whose ring is far smaller than the traffic, so that
+    producers must wait for room again and again."""
+    src = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    wd.fill(src.data_ptr(), 1 << 20, 3)
+    out = torch.zeros(n_msgs * msg_bytes + 64, dtype=torch.uint8, device="cuda")
+    ring = torch.zeros(P, dtype=torch.uint8, device="cuda")
+    ent = torch.zeros(E, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    ss, os_, rs, es = _reg(H, ctx, src), _reg(H, ctx, out), _reg(H, ctx, ring), _reg(H, ctx, ent)
+    mode = H.CH_MPSC_LOCK if locking else H.CH_SPSC
+    K = 2 if locking else 1
+    rc, ch = H.hicr_channel_create(ctx, H.make_channel_cfg(H.CH_VAR, mode, K, H.CH_DEVICE, rs, es,
+                                                           capacity=P, entries=E))
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    g = np.random.default_rng(n_msgs)
+    offs = (g.random(n_msgs) * ((1 << 20) - msg_bytes)).astype(np.uint64)
+    sizes = np.full(n_msgs, msg_bytes, dtype=np.uint64)
+    streams = [(ch, 0, ss, os_, 0, n_msgs)]
+    return ch, streams, offs, sizes, (src, out, ring, ent)
+
+
+@pytest.mark.parametrize("locking", [False, True])
+def test_pump_timeout_is_reported_and_breaks_the_channel(env, locking):
+    """A no-progress limit of one device-clock tick ends the pump at its
+    first wait: every wave exits, the fence reports HICR_ETIMEDOUT, the
+    channel refuses further pumps, and the context keeps working."""
+    torch, H, wd, ctx = env
+    _say("pump timeout", locking)
+    ch, streams, offs, sizes, keep = _blocking_rig(torch, H, wd, ctx, 2000, 4096, 8192, 4, locking)
+    assert H.hicr_channel_pump(ctx, streams, offs, sizes, timeout_ns=1) == H.OK
+    assert H.hicr_fence(ctx) == H.ETIMEDOUT
+    assert H.hicr_channel_pump(ctx, streams, offs, sizes) == H.EINVAL
+    assert H.hicr_fence(ctx) == H.OK
+    # the context still moves bytes
+    a = torch.arange(256, dtype=torch.uint8, device="cuda")
+    b = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    sa, sb = _reg(H, ctx, a), _reg(H, ctx, b)
+    assert H.hicr_memcpy(ctx, sb, 0, sa, 0, 256) == H.OK
+    assert H.hicr_fence(ctx) == H.OK
+    assert np.array_equal(b.cpu().numpy(), np.arange(256, dtype=np.uint8))
+    assert H.hicr_channel_destroy(ch) == H.OK
+
+
+def test_pump_abort_ends_a_running_pump(env):
+    """hicr_channel_abort while a long pump runs (60,000 messages through an
+    8 KiB ring): the pump ends early and the fence reports the abort."""
+    import time
+    torch, H, wd, ctx = env
+    _say("pump abort")
+    ch, streams, offs, sizes, keep = _blocking_rig(torch, H, wd, ctx, 60000, 4096, 8192, 4)
+    t0 = time.perf_counter()
+    assert H.hicr_channel_pump(ctx, streams, offs, sizes, timeout_ns=5 * 10**9) == H.OK
+    time.sleep(0.002)
+    assert H.hicr_channel_abort(ctx) == H.OK
+    rc = H.hicr_fence(ctx)
+    dt = time.perf_counter() - t0
+    assert rc == H.EDEVICE, (rc, H.hicr_last_error(ctx), dt)
+    assert "abort" in H.hicr_last_error(ctx)
+    assert H.hicr_channel_pump(ctx, streams, offs, sizes) == H.EINVAL
+    assert H.hicr_fence(ctx) == H.OK
+    assert H.hicr_channel_destroy(ch) == H.OK
