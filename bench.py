@@ -453,23 +453,25 @@ def bench_tiny(torch, H, reps=1000, warmup=50):
     return out
 
 
-def bench_halo(torch, H, N=704, Py=2, Pz=4, iters=200, reps=3):
-    """Jacobi halo exchange, 2 x 4 subdomains of 704^3 8-byte cells with a
-    ghost layer (22.5 GB): 20 faces x 704 rows of 5,632 B = 14,080 requests,
-    79 MB per exchange.  The 12 classes are autotuned on the exchange; then
-    `iters` exchanges run back to back (one fence at the end) as (a) one
-    hicr_memcpy_batch per exchange and (b) one replay of a persistent plan
-    per exchange, and one exchange + fence is timed alone for latency."""
+def bench_halo(torch, H, N=704, Py=2, Pz=22, h=2, iters=200, reps=3):
+    """The Jacobi test case's halo exchange: a 704^3 grid of 8-byte cells over
+    1 x 2 x 22 subgrids (the paper's best thread grid), ghost layers two
+    cells deep (13-point stencil), each subgrid in its own block (3.2 GB in
+    all): 61,952 row copies of 5,632 B = 349 MB per exchange.  The 12 classes
+    are autotuned on the exchange; then `iters` exchanges run back to back
+    (one fence at the end) as one hicr_memcpy_batch per exchange, and as a
+    replay of a persistent plan (direct and graph), and one exchange + fence
+    is timed alone for latency."""
     from workloads import halo
     stream = torch.cuda.Stream()
     rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
     assert rc == H.OK
-    sb = halo.sub_bytes(N)
+    sb = halo.sub_bytes(N, Py, Pz, h)
     pool = torch.empty(Py * Pz * sb, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     slots = np.array([H.hicr_slot_register(ctx, pool.data_ptr() + k * sb, sb)[1]
                       for k in range(Py * Pz)], dtype=np.uint32)
-    d = halo.exchange(N, Py, Pz)
+    d = halo.exchange(N, Py, Pz, h)
     d["dst_slot"], d["src_slot"] = slots[d["dst_slot"]], slots[d["src_slot"]]
     moved = 2 * int(d["size"].sum())
     rc, times, best = H.hicr_autotune(ctx, d, reps)
@@ -494,8 +496,8 @@ def bench_halo(torch, H, N=704, Py=2, Pz=4, iters=200, reps=3):
                 "latency_p50_us": round(float(np.percentile(lat, 50)), 2),
                 "latency_p99_us": round(float(np.percentile(lat, 99)), 2)}
 
-    out = {"workload": f"Jacobi halo exchange: {Py}x{Pz} subdomains of {N}^3 8-byte cells, "
-                       f"{len(d)} row copies of {N * 8} B per exchange",
+    out = {"workload": f"Jacobi halo exchange: {N}^3 8-byte cells over 1x{Py}x{Pz} subgrids, "
+                       f"ghost depth {h}, {len(d)} row copies of {N * 8} B per exchange",
            "requests": len(d), "bytes_rw": moved,
            "autotune_ms": [round(float(t), 4) for t in times], "best_class": int(best),
            "memcpy_batch": run(lambda: H.hicr_memcpy_batch(ctx, d, sched))}

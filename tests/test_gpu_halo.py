@@ -1,6 +1,7 @@
 """GPU parity of the Jacobi halo exchange (a persistent plan of row copies)
 against the oracle: whole pools at a small grid over several replays, and
-sampled rows at the full 704^3-per-subdomain size."""
+sampled rows at the paper's size (704^3 cells over 1 x 2 x 22 subgrids,
+ghost layers two cells deep)."""
 import numpy as np
 import pytest
 
@@ -26,13 +27,13 @@ def env():
     assert H.hicr_ctx_destroy(ctx) == H.OK
 
 
-def _rig(torch, H, ctx, N, Py, Pz):
-    sb = halo.sub_bytes(N)
+def _rig(torch, H, ctx, N, Py, Pz, h):
+    sb = halo.sub_bytes(N, Py, Pz, h)
     pool = torch.empty(Py * Pz * sb, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     slots = np.array([H.hicr_slot_register(ctx, pool.data_ptr() + s * sb, sb)[1]
                       for s in range(Py * Pz)], dtype=np.uint32)
-    d = halo.exchange(N, Py, Pz)
+    d = halo.exchange(N, Py, Pz, h)
     dd = d.copy()
     dd["dst_slot"], dd["src_slot"] = slots[d["dst_slot"]], slots[d["src_slot"]]
     return pool, slots, d, dd, sb
@@ -40,8 +41,8 @@ def _rig(torch, H, ctx, N, Py, Pz):
 
 def test_small_grid_plan_replays(env):
     torch, H, wd, ctx = env
-    N, Py, Pz = 37, 2, 3
-    pool, slots, d, dd, sb = _rig(torch, H, ctx, N, Py, Pz)
+    N, Py, Pz, h = 40, 2, 4, 2
+    pool, slots, d, dd, sb = _rig(torch, H, ctx, N, Py, Pz, h)
     rc, plan, _ = H.hicr_plan_create(ctx, dd, H.hicr_sched_class(0)[1], H.PLAN_GRAPH)
     assert rc == H.OK, H.hicr_last_error(ctx)
     L = Py * Pz * sb
@@ -65,12 +66,12 @@ def test_small_grid_plan_replays(env):
 
 
 def test_full_size_sampled_rows(env):
-    """N = 704, 2 x 4 subdomains (22.5 GB): one replay of the plan the
-    benchmark times; 300 sampled rows and the cells around them are checked
-    against the oracle's copy of each sampled request."""
+    """704^3 over 1 x 2 x 22 subgrids, h = 2 (3.2 GB, 61,952 rows): one
+    replay of the plan the benchmark times; 300 sampled rows and the cells
+    around them are checked against the oracle's copy of each request."""
     torch, H, wd, ctx = env
-    N, Py, Pz = 704, 2, 4
-    pool, slots, d, dd, sb = _rig(torch, H, ctx, N, Py, Pz)
+    N, Py, Pz, h = 704, 2, 22, 2
+    pool, slots, d, dd, sb = _rig(torch, H, ctx, N, Py, Pz, h)
     seed = 7200
     wd.fill(pool.data_ptr(), pool.numel(), seed)
     torch.cuda.synchronize()

@@ -64,41 +64,45 @@ def test_log_uniform_law():
 
 
 def test_halo_exchange_matches_array_slicing():
-    """The halo requests, applied by the oracle, fill every ghost face with
-    the neighbour's boundary plane -- checked against numpy slicing of the
-    same grids -- and touch nothing else."""
+    """The halo requests, applied by the oracle, fill every ghost face (h
+    planes deep) with the neighbour's boundary planes -- checked against
+    numpy slicing of the same grids -- and touch nothing else."""
     import oracle
     from workloads import halo
-    N, Py, Pz = 5, 3, 2
-    d = halo.exchange(N, Py, Pz)
-    assert len(d) == halo.n_faces(Py, Pz) * N
-    assert (d["size"] == N * 8).all()
-    g = np.random.default_rng(0)
-    grids = [g.integers(0, 2**62, size=(N + 2, N + 2, N + 2), dtype=np.int64)
-             for _ in range(Py * Pz)]                       # [z][y][x]
-    before = [a.copy() for a in grids]
-    oc = oracle.Ctx()
-    ids = [oc.register(a.view(np.uint8).reshape(-1))[1] for a in grids]
-    od = d.copy()
-    od["dst_slot"] = np.array(ids)[d["dst_slot"]]
-    od["src_slot"] = np.array(ids)[d["src_slot"]]
-    assert oc.hazard_check(od)[0] == oracle.OK
-    assert oc.memcpy_batch(od)[0] == oracle.OK
-    want = [a.copy() for a in before]
-    I = slice(1, N + 1)
-    for k in range(Pz):
-        for j in range(Py):
-            s = j + Py * k
-            if j + 1 < Py:
-                want[s][I, N + 1, I] = before[s + 1][I, 1, I]
-            if j > 0:
-                want[s][I, 0, I] = before[s - 1][I, N, I]
-            if k + 1 < Pz:
-                want[s][N + 1, I, I] = before[s + Py][1, I, I]
-            if k > 0:
-                want[s][0, I, I] = before[s - Py][N, I, I]
-    for s in range(Py * Pz):
-        assert np.array_equal(grids[s], want[s]), s
-    # sources are interior cells, destinations ghost cells, all in bounds
-    assert (d["dst_off"] + d["size"] <= halo.sub_bytes(N)).all()
-    assert (d["src_off"] + d["size"] <= halo.sub_bytes(N)).all()
+    for N, Py, Pz, h in [(12, 2, 3, 2), (10, 1, 5, 1), (8, 2, 2, 3)]:
+        nx, ny, nz = halo.dims(N, Py, Pz)
+        d = halo.exchange(N, Py, Pz, h)
+        assert len(d) == halo.n_requests(N, Py, Pz, h)
+        assert (d["size"] == nx * 8).all()
+        g = np.random.default_rng(N + h)
+        shape = (nz + 2 * h, ny + 2 * h, nx + 2 * h)             # [z][y][x]
+        grids = [g.integers(0, 2**62, size=shape, dtype=np.int64) for _ in range(Py * Pz)]
+        before = [a.copy() for a in grids]
+        oc = oracle.Ctx()
+        ids = [oc.register(a.view(np.uint8).reshape(-1))[1] for a in grids]
+        od = d.copy()
+        od["dst_slot"] = np.array(ids)[d["dst_slot"]]
+        od["src_slot"] = np.array(ids)[d["src_slot"]]
+        assert oc.hazard_check(od)[0] == oracle.OK
+        assert oc.memcpy_batch(od)[0] == oracle.OK
+        want = [a.copy() for a in before]
+        X = slice(h, nx + h)
+        Y = slice(h, ny + h)
+        Z = slice(h, nz + h)
+        for k in range(Pz):
+            for j in range(Py):
+                s = j + Py * k
+                if j + 1 < Py:
+                    want[s][Z, ny + h:ny + 2 * h, X] = before[s + 1][Z, h:2 * h, X]
+                if j > 0:
+                    want[s][Z, 0:h, X] = before[s - 1][Z, ny:ny + h, X]
+                if k + 1 < Pz:
+                    want[s][nz + h:nz + 2 * h, Y, X] = before[s + Py][h:2 * h, Y, X]
+                if k > 0:
+                    want[s][0:h, Y, X] = before[s - Py][nz:nz + h, Y, X]
+        for s in range(Py * Pz):
+            assert np.array_equal(grids[s], want[s]), (N, Py, Pz, h, s)
+        sb = halo.sub_bytes(N, Py, Pz, h)
+        assert (d["dst_off"] + d["size"] <= sb).all() and (d["src_off"] + d["size"] <= sb).all()
+    # the paper's best decomposition: 704^3 over 1 x 2 x 22, 13-point stencil (h = 2)
+    assert halo.n_requests(704, 2, 22, 2) == 61_952
