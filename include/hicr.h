@@ -12,14 +12,20 @@
  *                                          hicr_slot_counters
  *   Sec. 4.3    Channels frontend: circular buffers at the consumer, the
  *               producer waits while the buffer is full, SPSC and MPSC
- *               (locking / non-locking)  -> hicr_channel_*
+ *               (locking / non-locking)  -> hicr_channel_*, and inside the
+ *                                          caller's kernels hicr_device.h
+ *   Sec. 4.3    Data Objects frontend   -> hicr_dobj_*
+ *   Sec. 5      Test Case 1 (ping-pong) -> hicr_pingpong
+ *   Growth directions beyond the paper: persistent batches (hicr_plan_*),
+ *   schedule selection (hicr_autotune, hicr_tune_*, hicr_mlp_*) and a
+ *   continuous-batching server (hicr_serve).
  *
  * General conventions
  *   - Every function returns 0 (HICR_OK) or a negative HICR_E* code and never
  *     throws.  hicr_last_error() gives a human-readable reason for the last
  *     failure on a context.
  *   - Pointers named *_dev are device (HBM) addresses; all other pointers are
- *     host addresses.  "stream" arguments are hipStream_t values passed as
+ *     host addresses (a slot's own memory may be HBM or pinned host memory).  "stream" arguments are hipStream_t values passed as
  *     void*; NULL selects the context's own stream.
  *   - The caller owns every registered allocation and must keep it alive
  *     until the slot is deregistered.  The library owns its internal buffers.

@@ -332,10 +332,11 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, 
   }
 }
 
-// One consumer workgroup takes every message of one channel: each round it
-// looks at all of the channel's rings at once, takes up to kConsBatch
-// published messages (round robin over rings), copies them as one batch to
-// their streams' outputs and releases each ring's room with one store pair.
+// One consumer workgroup drains a set of independent rings, each with a
+// single producer stream (SPSC rings, non-locking MPSC sub-rings): each round
+// it looks at all of its rings at once, takes up to kConsBatch published
+// messages (round robin over rings), copies them as one batch to their
+// streams' outputs and releases each ring's room with one store pair.
 __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
   __shared__ uint64_t s_hm[kMaxProducers], s_hb[kMaxProducers];
   __shared__ uint64_t s_outpos[kMaxProducers], s_cnt[kMaxProducers];
@@ -355,7 +356,6 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
   __shared__ uint64_t s_rP[kMaxProducers], s_rE[kMaxProducers];
   __shared__ uint32_t s_psid[kMaxProducers];
   const DevChannel ch = a.chans[cid];
-  const bool locking = ch.mode == kModeMpscLock;
   const uint32_t lane = tid & 63, wave = tid >> 6;
   for (uint32_t i = tid; i < ch.n_rings; i += kPumpBlock) {
     const DevRing rg = a.rings[ch.first_ring + i];
@@ -447,9 +447,7 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
         const uint32_t ri = s_ring_of[i];
         const uint64_t e = s_ent[i];
         const uint64_t sz = e & kEntrySizeMask;
-        // a shared ring names its producer in the entry; an independent ring
-        // has one producer
-        const uint32_t p = locking ? (uint32_t)(e >> 48) % ch.K : ri;
+        const uint32_t p = ri;  // ring q carries producer stream q of the unit
         const uint64_t P = s_rP[ri];
         if (sz > P || s_outpos[p] + sz > s_pbytes[p] || s_cnt[p] >= s_pn[p]) {
           bad = 1;
@@ -462,8 +460,7 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
         if (sz > first) s_seg[nseg++] = make_seg(dst + first, s_rpay[ri], sz - first);
         s_rbytes[ri] += sz;
         s_outpos[p] += sz;
-        if (a.trace)
-          a.trace[locking ? ch.trace_base + done + i : s_ptrace[p] + s_cnt[p]] = s_psid[p];
+        if (a.trace) a.trace[s_ptrace[p] + s_cnt[p]] = s_psid[p];
         if (a.ts_pop) a.ts_pop[s_pfirst[p] + s_cnt[p]] = wall_clock64();
         s_cnt[p] += 1;
       }
