@@ -123,7 +123,8 @@ int hicr_ctx_set_sched(hicr_ctx ctx, const hicr_sched *s);
 /* Copy workgroups launched per compute unit (the persistent grid is at most
  * CUs x this, capped by what fits).  0 (the default) picks by schedule: 4 for
  * 4 KiB chunks, otherwise 1 at unroll 4 and 2 at unroll 2, and 2 when the
- * network chooses the class on the device.  Never changes a byte.
+ * network chooses the class on the device; at least 4 when the launch's
+ * average piece is under 16 KiB.  Never changes a byte.
  * wgs_per_cu > 64 -> HICR_EINVAL. */
 int hicr_ctx_set_copy_grid(hicr_ctx ctx, uint32_t wgs_per_cu);
 /* Memory-space pairs memcpy accepts from now on (HICR_PAIR bits; default
@@ -426,7 +427,7 @@ int hicr_channel_device_view(hicr_channel ch, uint32_t ring, hicr_dev_ring *out)
  * pushes `buf` into B.  rtt_ticks[i * reps + k] receives round trip k of size
  * i in 100 MHz device-clock ticks.  All five slots: HBM, 16-byte aligned, at
  * least max(sizes) bytes.  wgs_per_endpoint 0 picks max(1, min(256,
- * size / 1 MiB)).  Synchronous. */
+ * size / 64 KiB)).  Synchronous. */
 int hicr_pingpong(hicr_ctx ctx, hicr_slot src, hicr_slot dst, hicr_slot ring_a, hicr_slot ring_b,
                   hicr_slot buf, const uint64_t *sizes, uint32_t n_sizes, uint32_t reps,
                   uint32_t wgs_per_endpoint, uint64_t *rtt_ticks);

@@ -40,7 +40,8 @@ int hicr_pingpong(hicr_ctx c, hicr_slot src, hicr_slot dst, hicr_slot ring_a, hi
   if (hipMalloc(&d, words * 8) != hipSuccess) return fail(c, HICR_ENOMEM, "ping-pong words");
   for (uint32_t i = 0; i < n_sizes && rc == HICR_OK; i++) {
     uint64_t W = wgs_per_endpoint;
-    if (W == 0) W = std::max<uint64_t>(1, std::min<uint64_t>(256, sizes[i] >> 20));
+    // one workgroup copies ~10 GB/s; give every 64 KiB of message its own
+    if (W == 0) W = std::max<uint64_t>(1, std::min<uint64_t>(256, sizes[i] >> 16));
     W = std::min<uint64_t>(W, cap);
     PingPongArgs a;
     a.src = base[0];

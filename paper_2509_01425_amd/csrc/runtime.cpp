@@ -160,17 +160,25 @@ int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
   // piece count with the smallest chunk of any class.
   const uint32_t bound_chunk = sched_dev ? kChunks[0] : ds.chunk;
   const uint32_t bound_wgs = sched_dev ? 64u : ds.wgs;
-  const int per_cu = std::min(c->grid_per_cu > 0 ? c->grid_per_cu : default_grid_per_cu(ds, sched_dev != nullptr), c->occ);
-  const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)per_cu;
+  const int per_cu_class =
+      c->grid_per_cu > 0 ? c->grid_per_cu : default_grid_per_cu(ds, sched_dev != nullptr);
   uint64_t i0 = 0;
   while (i0 < n) {
-    uint64_t i1 = i0, pieces = 0;
+    uint64_t i1 = i0, pieces = 0, bytes = 0;
     while (i1 < n && i1 - i0 < kMaxLdsDescs) {
       uint64_t p = piece_count(hd[i1], hz[i1], bound_chunk, bound_wgs);
       if (i1 > i0 && pieces + p >= (1ull << 31)) break;
       pieces += p;
+      bytes += hz[i1];
       i1++;
     }
+    // Pieces of a few KiB are latency-bound (search, head and tail bytes, one
+    // or two vector rounds): when the average piece is under 16 KiB, four
+    // groups per CU let every wavefront start on its own piece at once.
+    int per_cu = per_cu_class;
+    if (c->grid_per_cu == 0 && bytes < pieces * (16u << 10)) per_cu = std::max(per_cu, 4);
+    per_cu = std::min(per_cu, c->occ);
+    const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)per_cu;
     if (pieces >= (1ull << 31))
       return fail(c, HICR_EINVAL, "request %llu needs more than 2^31 pieces",
                   (unsigned long long)i0);
