@@ -122,9 +122,8 @@ int hicr_last_error(hicr_ctx ctx, char *buf, size_t n);
 int hicr_ctx_set_sched(hicr_ctx ctx, const hicr_sched *s);
 /* Copy workgroups launched per compute unit (the persistent grid is at most
  * CUs x this, capped by what fits).  0 (the default) picks by schedule: 4 for
- * 4 KiB chunks, otherwise 1 at unroll 4 and 2 at unroll 2, and 2 when the
- * network chooses the class on the device; at least 4 when the launch's
- * average piece is under 16 KiB.  Never changes a byte.
+ * 4 KiB chunks, otherwise 1 at unroll 4 and 2 at unroll 2; at least 4 when
+ * the launch's average piece is under 16 KiB.  Never changes a byte.
  * wgs_per_cu > 64 -> HICR_EINVAL. */
 int hicr_ctx_set_copy_grid(hicr_ctx ctx, uint32_t wgs_per_cu);
 /* Memory-space pairs memcpy accepts from now on (HICR_PAIR bits; default
@@ -186,8 +185,7 @@ int hicr_fence_slot(hicr_ctx ctx, hicr_slot slot, uint64_t exp_sent, uint64_t ex
  * for replays as for any other transfer.
  *   d[0..n): requests as for hicr_memcpy_batch (copied; the caller may reuse
  *   the array at once).  s_or_null: FIXED, TUNED (resolved now) or LEARNED
- *   (the network runs once on the device now; every replay reads its choice
- *   from device memory).  On a rejected request: its code, *bad_index set, no
+ *   (the network runs once now, on the host; every replay uses its choice).  On a rejected request: its code, *bad_index set, no
  *   plan.  n = 0 gives a plan whose launches move nothing.
  * While a plan exists the slots it names cannot be deregistered (HICR_EBUSY).
  * Replays of one plan are serialised: a launch on another stream than the
@@ -230,11 +228,13 @@ int hicr_tune_lookup(hicr_ctx ctx, const hicr_desc *descs, uint64_t n, uint32_t 
 
 /* The schedule network, 32 -> 64 -> 64 -> 12 with ReLU, fp32, parameters in
  * the flat layout W1[64][32] b1[64] W2[64][64] b2[64] W3[12][64] b3[12]
- * (7,052 floats).  Loading parameters enables HICR_SCHED_LEARNED, in which a
- * device kernel computes the batch feature from the uploaded sizes, runs the
- * network and hands the argmax class (ties to the lowest) to the copy kernel
- * without a host round trip.  Without a network HICR_SCHED_LEARNED falls back
- * to the tuned table.  x_dev: [batch][32] features, y_dev: [batch] class
+ * (7,052 floats).  Training runs on the GPU (the kernels below); loading
+ * parameters enables HICR_SCHED_LEARNED, in which every submission (or plan
+ * creation) evaluates the network on the batch feature on the host -- the
+ * sizes are there already -- and takes the argmax class (ties to the lowest);
+ * after device training steps the parameters are read back once, at the next
+ * learned submission.  Without a network HICR_SCHED_LEARNED falls back to the
+ * tuned table.  x_dev: [batch][32] features, y_dev: [batch] class
  * labels, logits_dev: [batch][12], grad_dev: [7052] (all device memory).
  * Labels lie in [0, 12); a sample with a label outside that range gets a NaN
  * loss and contributes no gradient.  The kernels read and write these buffers
@@ -245,7 +245,7 @@ int hicr_mlp_set_params(hicr_ctx ctx, const float *params); /* also resets Adam 
 int hicr_mlp_get_params(hicr_ctx ctx, float *params_out);
 int hicr_mlp_forward(hicr_ctx ctx, const float *x_dev, uint32_t batch, float *logits_dev);
 /* Class the network chose for the most recent HICR_SCHED_LEARNED submission
- * (waits for that submission to complete). */
+ * or plan; HICR_EINVAL before the first. */
 int hicr_last_choice(hicr_ctx ctx, uint32_t *cls);
 /* Gradient of the mean softmax cross-entropy (and the mean loss, if loss_dev). */
 int hicr_mlp_grad(hicr_ctx ctx, const float *x_dev, const int32_t *y_dev, uint32_t batch,

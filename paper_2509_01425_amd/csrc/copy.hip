@@ -117,12 +117,10 @@ __device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s,
     copy_body<2>(d16, s16, nv, lane);
 }
 
-__global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s0,
-                                                          const DevSched *sched_dev) {
+__global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s) {
   __shared__ uint32_t ends[kMaxLdsDescs];
   __shared__ uint32_t wsum[kCopyBlock / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  DevSched s = sched_dev ? *sched_dev : s0;
   const uint32_t n = b.n;
 
   // 1. pieces per request, then an inclusive block scan in LDS
@@ -167,10 +165,9 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
   }
 }
 
-hipError_t launch_copy(const DevBatch &b, DevSched s, const DevSched *sched_dev, uint32_t grid,
-                       hipStream_t stream) {
+hipError_t launch_copy(const DevBatch &b, DevSched s, uint32_t grid, hipStream_t stream) {
   if (b.n > kMaxLdsDescs || grid == 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(kCopyBlock), 0, stream, b, s, sched_dev);
+  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(kCopyBlock), 0, stream, b, s);
   return hipGetLastError();
 }
 

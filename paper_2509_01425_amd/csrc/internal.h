@@ -22,8 +22,7 @@ struct DevBatch {
   uint32_t n;
 };
 
-// Schedule as the kernel sees it (a device word when a device-side selector
-// chose it).
+// Schedule as the kernel sees it.
 struct DevSched {
   uint32_t chunk, wgs, unroll, cls;
 };
@@ -53,9 +52,7 @@ __host__ __device__ inline uint64_t piece_count(uint64_t dst, uint64_t size, uin
 }
 
 // Launch the fused copy kernel over one sub-batch (n <= kMaxLdsDescs).
-// sched_dev, when not null, overrides `s` with a device-resident choice.
-hipError_t launch_copy(const DevBatch &b, DevSched s, const DevSched *sched_dev, uint32_t grid,
-                       hipStream_t stream);
+hipError_t launch_copy(const DevBatch &b, DevSched s, uint32_t grid, hipStream_t stream);
 // Raise the slot counters of n requests (slots[i] = dst | src << 32); queued
 // after the copy launches of the same requests on the same stream.
 hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters,

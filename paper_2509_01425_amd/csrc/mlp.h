@@ -25,8 +25,6 @@ hipError_t mlp_forward(const MlpBufs &m, const float *params, const float *X, in
 hipError_t mlp_backward(const MlpBufs &m, const float *params, const float *X, const int32_t *y,
                         int B, float *grad, float *loss_mean, hipStream_t s);
 hipError_t mlp_adam(float *p, const float *g, float *m, float *v, float lr, int t, hipStream_t s);
-hipError_t launch_sched_infer(const uint64_t *sizes, uint32_t n, const float *params,
-                              const DevSched *classes, DevSched *out, hipStream_t s);
 
 // Host mirror of the histogram feature: bin floor(log2 s) capped at 31,
 // size 0 in bin 0; feature log2(1 + count).

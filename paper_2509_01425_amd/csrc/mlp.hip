@@ -6,10 +6,6 @@
 // results are deterministic run to run.  Parameter layout (flat, row-major):
 // W1[64,32] b1[64] W2[64,64] b2[64] W3[12,64] b3[12].
 //
-// sched_infer_kernel runs inside a memcpy submission: one workgroup builds
-// the batch's 32-bin log2 size histogram in LDS, evaluates the network on
-// log2(1 + count) and writes the argmax class's schedule for the copy kernel
-// that follows on the same stream.
 #include "internal.h"
 #include "mlp.h"
 
@@ -104,64 +100,6 @@ __global__ __launch_bounds__(256) void adam_kernel(float *p, const float *g, flo
   p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// Histogram bin of a request size: floor(log2 s) capped at 31; size 0 -> 0.
-__device__ __forceinline__ int size_bin(uint64_t s) {
-  if (s == 0) return 0;
-  const int b = 63 - __clzll((long long)s);
-  return b > 31 ? 31 : b;
-}
-
-__global__ __launch_bounds__(256) void sched_infer_kernel(const uint64_t *sizes, uint32_t n,
-                                                          const float *params,
-                                                          const DevSched *classes,
-                                                          DevSched *out) {
-  __shared__ uint32_t hist[kMlpIn];
-  __shared__ float x[kMlpIn], h1[kMlpHidden], h2[kMlpHidden], z[kMlpOut];
-  // The parameters (28 KiB) are staged in LDS with coalesced 16-byte loads:
-  // after a large copy they are no longer in the caches, and the dot products
-  // below would otherwise wait on one uncoalesced load chain per layer.
-  __shared__ float4 P4[kMlpParams / 4];
-  static_assert(kMlpParams % 4 == 0, "parameter block is a whole number of float4");
-  const int t = threadIdx.x;
-  for (int i = t; i < kMlpParams / 4; i += 256) P4[i] = reinterpret_cast<const float4 *>(params)[i];
-  if (t < kMlpIn) hist[t] = 0;
-  __syncthreads();
-  for (uint32_t i = t; i < n; i += 256) atomicAdd(&hist[size_bin(sizes[i])], 1u);
-  __syncthreads();
-  if (t < kMlpIn) x[t] = log2f(1.f + (float)hist[t]);
-  __syncthreads();
-  const float *P = reinterpret_cast<const float *>(P4);
-  const float *W1 = P, *b1 = W1 + kMlpHidden * kMlpIn, *W2 = b1 + kMlpHidden,
-              *b2 = W2 + kMlpHidden * kMlpHidden, *W3 = b2 + kMlpHidden,
-              *b3 = W3 + kMlpOut * kMlpHidden;
-  if (t < kMlpHidden) {
-    float a = b1[t];
-    for (int i = 0; i < kMlpIn; i++) a = fmaf(W1[t * kMlpIn + i], x[i], a);
-    h1[t] = a > 0.f ? a : 0.f;
-  }
-  __syncthreads();
-  if (t < kMlpHidden) {
-    float a = b2[t];
-    for (int i = 0; i < kMlpHidden; i++) a = fmaf(W2[t * kMlpHidden + i], h1[i], a);
-    h2[t] = a > 0.f ? a : 0.f;
-  }
-  __syncthreads();
-  if (t < kMlpOut) {
-    float a = b3[t];
-    for (int i = 0; i < kMlpHidden; i++) a = fmaf(W3[t * kMlpHidden + i], h2[i], a);
-    z[t] = a;
-  }
-  __syncthreads();
-  if (t == 0) {
-    int best = 0;
-    for (int c = 1; c < kMlpOut; c++)
-      if (z[c] > z[best]) best = c;  // ties go to the lowest class
-    DevSched s = classes[best];
-    s.cls = (uint32_t)best;
-    *out = s;
-  }
-}
-
 static inline unsigned blocks(int n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t mlp_forward(const MlpBufs &m, const float *params, const float *X, int B,
@@ -207,13 +145,6 @@ hipError_t mlp_adam(float *p, const float *g, float *mo, float *ve, float lr, in
   const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
   hipLaunchKernelGGL(adam_kernel, dim3(blocks(kMlpParams)), dim3(256), 0, s, p, g, mo, ve,
                      kMlpParams, lr, b1, b2, 1e-8f, bc1, bc2);
-  return hipGetLastError();
-}
-
-hipError_t launch_sched_infer(const uint64_t *sizes, uint32_t n, const float *params,
-                              const DevSched *classes, DevSched *out, hipStream_t s) {
-  hipLaunchKernelGGL(sched_infer_kernel, dim3(1), dim3(256), 0, s, sizes, n, params, classes,
-                     out);
   return hipGetLastError();
 }
 

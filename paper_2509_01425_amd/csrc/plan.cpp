@@ -23,12 +23,10 @@ struct hicr_plan_s {
   hicr_ctx c = nullptr;
   uint64_t n = 0;
   void *d = nullptr;          // device SoA {dst, src, size, slot pair}, 32 B per request
-  char *words = nullptr;      // device-chosen schedule (offset 16)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;  // HICR_PLAN_GRAPH
   std::vector<uint64_t> h;        // host copy of the packed requests (direct replay)
   DevSched ds{};
-  const DevSched *sched_dev = nullptr;
   hipEvent_t ev = nullptr;    // end of the last replay
   hipStream_t last = nullptr; // stream of the last replay
   bool launched = false;
@@ -42,7 +40,6 @@ void free_plan(hicr_plan p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->ev) (void)hipEventDestroy(p->ev);
   if (p->d) (void)hipFree(p->d);
-  if (p->words) (void)hipFree(p->words);
   for (hicr_slot s : p->slots) p->c->slots[s].plan_refs--;
   delete p;
 }
@@ -104,9 +101,9 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
     }
   }
   hicr_sched sched = s ? *s : c->def_sched;
-  bool learned = false;
   if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
-    int rc = choose_sched(c, d, n, sched.mode, &sched, &learned);
+    // resolved once: every replay uses the class chosen now
+    int rc = choose_sched(c, d, n, sched.mode, &sched);
     if (rc != HICR_OK) return rc;
   } else if (sched.mode != HICR_SCHED_FIXED) {
     return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
@@ -133,8 +130,6 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
   pack_batch(c, d, n, h.data());
   hipStream_t cs = nullptr;
   hipError_t e = hipEventCreateWithFlags(&p->ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMalloc(&p->words, 64);
-  if (e == hipSuccess) e = hipMemset(p->words, 0, 64);
   if (e == hipSuccess && n) e = hipMalloc(&p->d, n * 32);
   if (e == hipSuccess && n) e = hipMemcpy(p->d, h.data(), n * 32, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -145,25 +140,11 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
   }
   const uint64_t *dd = static_cast<const uint64_t *>(p->d);
   DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
-  const DevSched *sched_dev = nullptr;
-  if (learned && n) {
-    // the network chooses once, from the uploaded sizes; replays read the choice
-    DevSched *choice = reinterpret_cast<DevSched *>(p->words + 16);
-    e = sched_infer(c, dd + 2 * n, n, choice, cs);
-    if (e == hipSuccess) e = hipStreamSynchronize(cs);
-    if (e != hipSuccess) {
-      (void)hipStreamDestroy(cs);
-      free_plan(p);
-      return hip_fail(c, e, "schedule inference for a plan");
-    }
-    sched_dev = choice;
-  }
   p->ds = ds;
-  p->sched_dev = sched_dev;
   if (flags & HICR_PLAN_GRAPH) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-      rc = launch_batch(c, dd, n, h.data(), h.data() + 2 * n, ds, sched_dev, c->d_counters, cs);
+      rc = launch_batch(c, dd, n, h.data(), h.data() + 2 * n, ds, c->d_counters, cs);
       hipGraph_t graph = nullptr;
       hipError_t e2 = hipStreamEndCapture(cs, &graph);
       p->graph = graph;
@@ -200,8 +181,8 @@ int hicr_plan_launch(hicr_plan p, void *stream) {
     e = hipGraphLaunch(p->exec, s);
   } else if (e == hipSuccess && p->n) {
     const uint64_t *dd = static_cast<const uint64_t *>(p->d);
-    int rc = launch_batch(c, dd, p->n, p->h.data(), p->h.data() + 2 * p->n, p->ds, p->sched_dev,
-                          c->d_counters, s);
+    int rc = launch_batch(c, dd, p->n, p->h.data(), p->h.data() + 2 * p->n, p->ds, c->d_counters,
+                          s);
     if (rc != HICR_OK) return rc;
   }
   if (e == hipSuccess) e = hipEventRecord(p->ev, s);

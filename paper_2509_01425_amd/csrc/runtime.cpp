@@ -146,27 +146,20 @@ static int alloc_counters(hicr_ctx c) {
 // batched workload (256 CUs): with 64 KiB or 1 MiB pieces one workgroup per CU
 // (four wavefronts) saturates HBM at unroll 4 and two do at unroll 2; more
 // groups only add contention.  4 KiB pieces spend more time per piece on the
-// search and want four.  A class chosen on the device is not known here: two.
-int default_grid_per_cu(const DevSched &ds, bool device_choice) {
-  if (device_choice) return 2;
+// search and want four.
+int default_grid_per_cu(const DevSched &ds) {
   if (ds.chunk <= (4u << 10)) return 4;
   return ds.unroll >= 4 ? 1 : 2;
 }
 
 int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
-                 const uint64_t *hz, DevSched ds, const DevSched *sched_dev, uint64_t *counters,
-                 hipStream_t stream) {
-  // With a device-side choice the host does not know the chunk; bound the
-  // piece count with the smallest chunk of any class.
-  const uint32_t bound_chunk = sched_dev ? kChunks[0] : ds.chunk;
-  const uint32_t bound_wgs = sched_dev ? 64u : ds.wgs;
-  const int per_cu_class =
-      c->grid_per_cu > 0 ? c->grid_per_cu : default_grid_per_cu(ds, sched_dev != nullptr);
+                 const uint64_t *hz, DevSched ds, uint64_t *counters, hipStream_t stream) {
+  const int per_cu_class = c->grid_per_cu > 0 ? c->grid_per_cu : default_grid_per_cu(ds);
   uint64_t i0 = 0;
   while (i0 < n) {
     uint64_t i1 = i0, pieces = 0, bytes = 0;
     while (i1 < n && i1 - i0 < kMaxLdsDescs) {
-      uint64_t p = piece_count(hd[i1], hz[i1], bound_chunk, bound_wgs);
+      uint64_t p = piece_count(hd[i1], hz[i1], ds.chunk, ds.wgs);
       if (i1 > i0 && pieces + p >= (1ull << 31)) break;
       pieces += p;
       bytes += hz[i1];
@@ -186,7 +179,7 @@ int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
     // every wavefront of a workgroup copies its own piece
     const uint64_t want = (pieces + kCopyBlock / 64 - 1) / (kCopyBlock / 64);
     uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), cap_grid);
-    hipError_t e = launch_copy(b, ds, sched_dev, grid, stream);
+    hipError_t e = launch_copy(b, ds, grid, stream);
     if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
     i0 = i1;
   }
@@ -208,7 +201,7 @@ void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h) {
 }
 
 // Validate, pack and launch n requests as one submission.
-int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, bool learned,
+int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
            hipStream_t stream, uint64_t *bad, const SubmitOpts *opt) {
   for (uint64_t i = 0; i < n; i++) {
     int rc = check_desc(c, d[i]);
@@ -231,20 +224,12 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, 
   if (e != hipSuccess) return hip_fail(c, e, "uploading a batch");
   const uint64_t *dd = static_cast<const uint64_t *>(s.d);
   DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
-  const DevSched *sched_dev = nullptr;
-  if (learned) {
-    // the network picks the class on the device, from the uploaded sizes
-    e = sched_infer(c, dd + 2 * n, n, s.sched_dev, stream);
-    if (e != hipSuccess) return hip_fail(c, e, "launching schedule inference");
-    sched_dev = s.sched_dev;
-    c->last_learned_sub = (int)(&s - c->subs);
-  }
   uint64_t *counters = (opt && opt->no_count) ? nullptr : c->d_counters;
   if (opt && opt->t0) {
     e = hipEventRecord(opt->t0, stream);
     if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
   }
-  rc = launch_batch(c, dd, n, h, h + 2 * n, ds, sched_dev, counters, stream);
+  rc = launch_batch(c, dd, n, h, h + 2 * n, ds, counters, stream);
   if (rc != HICR_OK) return rc;
   if (opt && opt->t1) {
     e = hipEventRecord(opt->t1, stream);
@@ -261,7 +246,7 @@ int flush_pending(hicr_ctx c) {
   std::vector<hicr_desc> p;
   p.swap(c->pending);
   uint64_t bad = 0;
-  return submit(c, p.data(), p.size(), c->def_sched, false, c->stream, &bad, nullptr);
+  return submit(c, p.data(), p.size(), c->def_sched, c->stream, &bad, nullptr);
 }
 
 }  // namespace hicr
@@ -329,15 +314,12 @@ int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
     c->own_stream = true;
   }
   bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipMalloc(&c->d_words, kNumSubs * 64) == hipSuccess;
-  ok = ok && hipMemset(c->d_words, 0, kNumSubs * 64) == hipSuccess;
   ok = ok && hipHostMalloc(&c->h_read, 64, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&c->push_ev, hipEventDisableTiming) == hipSuccess;
   if (ok && (pump_occupancy(&c->pump_occ) != 0 || c->pump_occ < 1)) c->pump_occ = 1;
   for (int i = 0; ok && i < kNumSubs; i++) {
     ok = hipEventCreateWithFlags(&c->subs[i].ev, hipEventDisableTiming) == hipSuccess;
-    c->subs[i].sched_dev = reinterpret_cast<DevSched *>(c->d_words + 64 * i + 16);
   }
   c->def_sched = hicr_sched{64u << 10, 1, 2, HICR_SCHED_FIXED};
   if (!ok || alloc_counters(c) != HICR_OK) {
@@ -361,7 +343,6 @@ int hicr_ctx_destroy(hicr_ctx c) {
     if (s.ev) (void)hipEventDestroy(s.ev);
   }
   if (c->d_counters) (void)hipFree(c->d_counters);
-  if (c->d_words) (void)hipFree(c->d_words);
   if (c->h_read) (void)hipHostFree(c->h_read);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   if (c->abort_stream) (void)hipStreamDestroy(c->abort_stream);
@@ -505,9 +486,8 @@ int hicr_memcpy_batch(hicr_ctx c, const hicr_desc *descs, uint64_t n, const hicr
   std::lock_guard<std::mutex> g(c->mu);
   (void)hipSetDevice(c->device);
   hicr_sched sched = s ? *s : c->def_sched;
-  bool learned = false;
   if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
-    int rc = choose_sched(c, descs, n, sched.mode, &sched, &learned);
+    int rc = choose_sched(c, descs, n, sched.mode, &sched);
     if (rc != HICR_OK) return rc;
   } else if (sched.mode != HICR_SCHED_FIXED) {
     return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
@@ -516,7 +496,7 @@ int hicr_memcpy_batch(hicr_ctx c, const hicr_desc *descs, uint64_t n, const hicr
   if (rc != HICR_OK) return rc;
   rc = flush_pending(c);
   if (rc != HICR_OK) return rc;
-  return submit(c, descs, n, sched, learned,
+  return submit(c, descs, n, sched,
                 stream ? static_cast<hipStream_t>(stream) : c->stream, bad, nullptr);
 }
 

@@ -33,7 +33,6 @@ struct Sub {
   uint64_t cap = 0;
   hipEvent_t ev = nullptr;
   bool inflight = false;
-  DevSched *sched_dev = nullptr;  // schedule chosen on the device (learned mode)
 };
 
 // Extra controls of one submission (autotuner).
@@ -74,14 +73,12 @@ struct hicr_ctx_s {
   std::vector<hicr::Slot> slots;
   uint64_t *d_counters = nullptr;  // [slot] = {sent, recv}
   uint32_t counter_cap = 0;
-  char *d_words = nullptr;  // small device words (device-chosen schedule per submission)
   uint64_t *h_read = nullptr;  // pinned read-back buffer
   hicr::Sub subs[hicr::kNumSubs];
   int next_sub = 0;
   std::vector<hicr_desc> pending;
   hicr_sched def_sched{};
   hicr::SchedState *sched = nullptr;
-  int last_learned_sub = -1;  // submission whose class the device chose last
   std::vector<struct hicr_channel_s *> channels;
   std::vector<struct hicr_plan_s *> plans;
   std::map<uint64_t, hicr_dobj_handle> dobjs;  // published data objects by id
@@ -106,7 +103,7 @@ bool any_inflight(hicr_ctx c);
 // Wait for an event: poll briefly, then block.
 hipError_t sync_event(hipEvent_t e);
 int wait_all(hicr_ctx c);
-int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched, bool learned,
+int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
            hipStream_t stream, uint64_t *bad, const SubmitOpts *opt);
 int flush_pending(hicr_ctx c);
 // Resolve requests to the structure of arrays {dst, src, size, slot pair}.
@@ -114,20 +111,17 @@ void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h);
 // Launch the copy kernel over an uploaded batch, one launch per sub-batch of
 // at most kMaxLdsDescs requests (hd/hz: host copies of dst and size).
 int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
-                 const uint64_t *hz, DevSched ds, const DevSched *sched_dev, uint64_t *counters,
-                 hipStream_t stream);
+                 const uint64_t *hz, DevSched ds, uint64_t *counters, hipStream_t stream);
 
 // Persistent batch plans (plan.cpp).
 int wait_plans(hicr_ctx c);
 bool plans_inflight(hicr_ctx c);
 void destroy_plans(hicr_ctx c);
 
-// Schedule selection (sched.cpp).  For mode LEARNED with a loaded network
-// *learned is set and the class is picked on the device during submission.
-int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out,
-                 bool *learned);
-hipError_t sched_infer(hicr_ctx c, const uint64_t *sizes_dev, uint64_t n, DevSched *out,
-                       hipStream_t stream);
+// Schedule selection (sched.cpp): the class for a batch under mode TUNED
+// (nearest tuned-table entry) or LEARNED (the network, evaluated on the host);
+// the context default when neither has data.
+int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out);
 void destroy_sched(hicr_ctx c);
 
 // Channel pushes and pumps (channel.cpp).

@@ -1,7 +1,9 @@
 // sched.cpp -- choosing a batch's copy schedule: the autotuner (times every
 // class on a batch), the tuned table (nearest autotuned batch by histogram
-// feature), and the device-resident network (trained by the project's own
-// HIP kernels, evaluated inside the submission).
+// feature), and the schedule network (trained on the GPU by the project's own
+// HIP kernels; evaluated for each submission on the host, where the batch's
+// sizes already are, so the choice costs no extra launch and the copy grid
+// can be sized for the chosen class).
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -21,9 +23,13 @@ struct SchedState {
   float *d_act = nullptr;  // activations of up to act_cap samples
   int act_cap = 0;
   MlpBufs bufs{};
-  DevSched *d_classes = nullptr;  // the 12 class schedules
   std::vector<std::array<float, kMlpIn>> feats;  // tuned table
   std::vector<uint32_t> cls;
+  // host copy of the network for the per-submission choice; stale after a
+  // device training step until the next learned submission reads it back
+  std::vector<float> h_params;
+  bool h_stale = false;
+  int last_cls = -1;  // class of the most recent learned submission
 };
 
 void batch_features(const uint64_t *sizes, uint64_t n, size_t stride, float *out) {
@@ -45,17 +51,7 @@ static int state(hicr_ctx c, SchedState **out) {
     const size_t pb = sizeof(float) * kMlpParams;
     bool ok = hipMalloc(&s->d_params, pb) == hipSuccess && hipMalloc(&s->d_m, pb) == hipSuccess &&
               hipMalloc(&s->d_v, pb) == hipSuccess && hipMalloc(&s->d_grad, pb) == hipSuccess &&
-              hipMalloc(&s->d_loss, 64) == hipSuccess &&
-              hipMalloc(&s->d_classes, sizeof(DevSched) * kMlpOut) == hipSuccess;
-    if (ok) {
-      DevSched cl[kMlpOut];
-      for (uint32_t k = 0; k < (uint32_t)kMlpOut; k++) {
-        hicr_sched h;
-        hicr_sched_class(k, &h);
-        cl[k] = DevSched{h.chunk_bytes, h.wgs_per_desc, h.unroll, k};
-      }
-      ok = hipMemcpy(s->d_classes, cl, sizeof cl, hipMemcpyHostToDevice) == hipSuccess;
-    }
+              hipMalloc(&s->d_loss, 64) == hipSuccess;
     c->sched = s;
     if (!ok) return fail(c, HICR_ENOMEM, "network state");
   }
@@ -111,14 +107,50 @@ static uint32_t nearest(const SchedState *s, const float *f) {
   return best;
 }
 
-int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out,
-                 bool *learned) {
-  *learned = false;
+// The network's class for one batch feature: forward pass in fp32 on the
+// host copy of the parameters (layout W1 b1 W2 b2 W3 b3), argmax with ties to
+// the lowest class -- the same arithmetic order as the device forward kernel.
+static uint32_t net_class(const float *P, const float *x) {
+  const float *W1 = P, *b1 = W1 + kMlpHidden * kMlpIn, *W2 = b1 + kMlpHidden,
+              *b2 = W2 + kMlpHidden * kMlpHidden, *W3 = b2 + kMlpHidden,
+              *b3 = W3 + kMlpOut * kMlpHidden;
+  float h1[kMlpHidden], h2[kMlpHidden], z[kMlpOut];
+  for (int o = 0; o < kMlpHidden; o++) {
+    float a = b1[o];
+    for (int i = 0; i < kMlpIn; i++) a = std::fmaf(W1[o * kMlpIn + i], x[i], a);
+    h1[o] = a > 0.f ? a : 0.f;
+  }
+  for (int o = 0; o < kMlpHidden; o++) {
+    float a = b2[o];
+    for (int i = 0; i < kMlpHidden; i++) a = std::fmaf(W2[o * kMlpHidden + i], h1[i], a);
+    h2[o] = a > 0.f ? a : 0.f;
+  }
+  uint32_t best = 0;
+  for (int o = 0; o < kMlpOut; o++) {
+    float a = b3[o];
+    for (int i = 0; i < kMlpHidden; i++) a = std::fmaf(W3[o * kMlpHidden + i], h2[i], a);
+    z[o] = a;
+    if (z[o] > z[best]) best = (uint32_t)o;
+  }
+  return best;
+}
+
+int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out) {
   SchedState *s = c->sched;
   if (mode == HICR_SCHED_LEARNED && s && s->net_loaded) {
-    *learned = true;
-    *out = c->def_sched;  // placeholder for host-side validation
-    return HICR_OK;
+    if (s->h_stale) {
+      // parameters changed by device training steps queued on the context stream
+      hipError_t e = hipMemcpyAsync(s->h_params.data(), s->d_params, sizeof(float) * kMlpParams,
+                                    hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "reading the network parameters");
+      s->h_stale = false;
+    }
+    float f[kMlpIn];
+    batch_features(n ? &d[0].size : nullptr, n, sizeof(hicr_desc), f);
+    const uint32_t k = net_class(s->h_params.data(), f);
+    s->last_cls = (int)k;
+    return hicr_sched_class(k, out);
   }
   // tuned table, the fallback when no network is loaded; default if empty
   if (s && !s->feats.empty() && n) {
@@ -130,17 +162,11 @@ int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr
   return HICR_OK;
 }
 
-hipError_t sched_infer(hicr_ctx c, const uint64_t *sizes_dev, uint64_t n, DevSched *out,
-                       hipStream_t stream) {
-  return launch_sched_infer(sizes_dev, (uint32_t)n, c->sched->d_params, c->sched->d_classes, out,
-                            stream);
-}
-
 void destroy_sched(hicr_ctx c) {
   SchedState *s = c->sched;
   if (!s) return;
   for (void *p : {(void *)s->d_params, (void *)s->d_m, (void *)s->d_v, (void *)s->d_grad,
-                  (void *)s->d_loss, (void *)s->d_act, (void *)s->d_classes})
+                  (void *)s->d_loss, (void *)s->d_act})
     if (p) (void)hipFree(p);
   delete s;
   c->sched = nullptr;
@@ -178,6 +204,8 @@ int hicr_mlp_set_params(hicr_ctx c, const float *params) {
   if (e != hipSuccess) return hip_fail(c, e, "loading network parameters");
   s->step = 0;
   s->net_loaded = true;
+  s->h_params.assign(params, params + kMlpParams);
+  s->h_stale = false;
   return HICR_OK;
 }
 
@@ -243,20 +271,15 @@ int hicr_mlp_train_step(hicr_ctx c, const float *x_dev, const int32_t *y_dev, ui
   if (e == hipSuccess) e = hipEventRecord(c->push_ev, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "network training step");
   c->push_pending = true;
+  s->h_stale = true;
   return HICR_OK;
 }
 
 int hicr_last_choice(hicr_ctx c, uint32_t *cls) {
   if (!c || !cls) return HICR_EINVAL;
   std::lock_guard<std::mutex> g(c->mu);
-  if (c->last_learned_sub < 0) return fail(c, HICR_EINVAL, "no learned submission yet");
-  (void)hipSetDevice(c->device);
-  Sub &s = c->subs[c->last_learned_sub];
-  hipError_t e = sync_event(s.ev);
-  DevSched d{};
-  if (e == hipSuccess) e = hipMemcpy(&d, s.sched_dev, sizeof d, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(c, e, "reading the chosen class");
-  *cls = d.cls;
+  if (!c->sched || c->sched->last_cls < 0) return fail(c, HICR_EINVAL, "no learned submission yet");
+  *cls = (uint32_t)c->sched->last_cls;
   return HICR_OK;
 }
 
@@ -313,14 +336,14 @@ int hicr_autotune(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t reps,
     hicr_sched_class(k, &sch);
     SubmitOpts warm;
     warm.no_count = true;
-    rc = submit(c, descs, n, sch, false, c->stream, &bad, &warm);
+    rc = submit(c, descs, n, sch, c->stream, &bad, &warm);
     std::vector<float> ms(reps);
     for (uint32_t r = 0; r < reps && rc == HICR_OK; r++) {
       SubmitOpts o;
       o.no_count = true;
       o.t0 = t0[r];
       o.t1 = t1[r];
-      rc = submit(c, descs, n, sch, false, c->stream, &bad, &o);
+      rc = submit(c, descs, n, sch, c->stream, &bad, &o);
     }
     if (rc == HICR_OK) rc = wait_all(c);
     for (uint32_t r = 0; r < reps && rc == HICR_OK; r++)

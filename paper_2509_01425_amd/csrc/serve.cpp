@@ -244,10 +244,9 @@ int hicr_serve(hicr_ctx c, const hicr_request *rq, uint64_t n, const hicr_serve_
         uint64_t bad = 0;
         Launch L;
         hicr_sched sched = base;
-        bool learned = false;
         if (base.mode != HICR_SCHED_FIXED)
-          rc = choose_sched(c, dbuf.data(), dbuf.size(), base.mode, &sched, &learned);
-        if (rc == HICR_OK) rc = submit(c, dbuf.data(), dbuf.size(), sched, learned, s, &bad, nullptr);
+          rc = choose_sched(c, dbuf.data(), dbuf.size(), base.mode, &sched);
+        if (rc == HICR_OK) rc = submit(c, dbuf.data(), dbuf.size(), sched, s, &bad, nullptr);
         if (rc == HICR_OK && hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess)
           rc = fail(c, HICR_EDEVICE, "serving event");
         if (rc == HICR_OK && hipEventRecord(L.ev, s) != hipSuccess)

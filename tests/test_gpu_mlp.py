@@ -145,8 +145,9 @@ def test_out_of_range_labels_give_nan_loss_and_no_gradient(env):
 
 
 def test_learned_submission_picks_oracle_class_and_moves_bytes(env):
-    """HICR_SCHED_LEARNED: the class chosen on the device equals the oracle
-    network's argmax on the oracle's feature, and the bytes are exact."""
+    """HICR_SCHED_LEARNED: the class the library's network picks for the
+    batch equals the oracle network's argmax on the oracle's feature, and the
+    bytes are exact."""
     torch, H, ctx = env
     import oracle
     from workloads import device as wd
