@@ -1,14 +1,19 @@
 // copy.hip -- fused batched memcpy for gfx950 (CDNA4).
 //
-// One launch moves a whole batch of memcpy(dst, dstOff, src, srcOff, size)
+// One launch moves a batch of memcpy(dst, dstOff, src, srcOff, size)
 // requests (HiCR Sec. 3.1.4) with a persistent grid:
-//   1. every workgroup computes the number of pieces of each request and an
-//      inclusive prefix scan of those counts into LDS (wavefront scans with
-//      __shfl_up, then a cross-wave carry), so the batch becomes one global
-//      index space of pieces;
-//   2. every wavefront is an independent worker: wave w of workgroup g
-//      takes pieces 4g + w, 4g + w + 4G, ...; a 64-ary search over the LDS
-//      table (two ballots for 4,096 requests) finds the request;
+//   1. the batch becomes one global index space of pieces: an inclusive
+//      prefix scan of the pieces per request.  A batch of at most 4,096
+//      requests is scanned by every workgroup into LDS (wavefront scans with
+//      __shfl_up, then a cross-wave carry); a larger one is scanned once, by
+//      one workgroup of scan_kernel staging 8,192 requests at a time in LDS,
+//      into a table in device memory that every copy workgroup then reads;
+//   2. every wavefront is an independent worker.  Against an LDS table,
+//      wave w of workgroup g takes pieces 4g + w, 4g + w + 4G, ... and finds
+//      each piece's request by a 64-ary ballot search (two ballots for 4,096
+//      requests).  Against a device-memory table, every wavefront takes one
+//      contiguous range of pieces, searches once for its first request and
+//      then walks forward request by request;
 //   3. a piece is copied by its wave with 16-byte destination-aligned vector
 //      stores and 16-byte loads at whatever alignment the source has (the HSA
 //      ABI runs gfx950 in unaligned-access mode), `unroll` vectors in flight
@@ -45,8 +50,10 @@ __device__ __forceinline__ void copy_byte(uint64_t d, uint64_t s) {
 }
 
 // First index i in [0, n) with ends[i] > q (ends strictly increasing, q <
-// ends[n-1]).  Every lane of the wave returns the same value.
-__device__ __forceinline__ uint32_t find_piece_owner(const uint32_t *ends, uint32_t n, uint32_t q,
+// ends[n-1]; ends in LDS or device memory).  Every lane of the wave returns
+// the same value.
+template <typename Ends>
+__device__ __forceinline__ uint32_t find_piece_owner(Ends ends, uint32_t n, uint32_t q,
                                                      uint32_t lane) {
   uint32_t lo = 0, hi = n;
   while (hi - lo > 64) {
@@ -117,6 +124,18 @@ __device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s,
     copy_body<2>(d16, s16, nv, lane);
 }
 
+// Piece j (of length L) of the request dst <- src, size bytes: pieces start
+// at line boundaries of the destination, the first and last clipped to the
+// request.
+__device__ __forceinline__ void copy_piece(uint64_t dst, uint64_t src, uint64_t size, uint64_t L,
+                                           uint32_t j, uint32_t unroll, uint32_t lane) {
+  const uint64_t base = dst & ~(uint64_t)(kLineBytes - 1);
+  uint64_t lo = base + (uint64_t)j * L, hi = lo + L;
+  if (lo < dst) lo = dst;
+  if (hi > dst + size) hi = dst + size;
+  if (lo < hi) copy_range(lo, hi, src + (lo - dst), unroll, lane);
+}
+
 __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s) {
   __shared__ uint32_t ends[kMaxLdsDescs];
   __shared__ uint32_t wsum[kCopyBlock / 64];
@@ -156,18 +175,114 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
     uint32_t i = __builtin_amdgcn_readfirstlane(find_piece_owner(ends, n, q, lane));
     uint32_t j = q - (i ? ends[i - 1] : 0u);
     const uint64_t dst = b.dst[i], src = b.src[i], size = b.size[i];
-    const uint64_t L = piece_len(dst, size, s.chunk, s.wgs);
-    const uint64_t base = dst & ~(uint64_t)(kLineBytes - 1);
-    uint64_t lo = base + (uint64_t)j * L, hi = lo + L;
-    if (lo < dst) lo = dst;
-    if (hi > dst + size) hi = dst + size;
-    if (lo < hi) copy_range(lo, hi, src + (lo - dst), s.unroll, lane);
+    copy_piece(dst, src, size, piece_len(dst, size, s.chunk, s.wgs), j, s.unroll, lane);
+  }
+}
+
+// Pieces per request and their inclusive prefix scan for a whole batch, by
+// one workgroup: rounds of kScanBlock x kScanPer requests, counted coalesced
+// into LDS, scanned kScanPer consecutive entries per thread, wavefront scans
+// of the per-thread sums, a cross-wave carry, and a carry across rounds.
+constexpr int kScanPer = 8;
+__global__ __launch_bounds__(kScanBlock) void scan_kernel(DevBatch b, DevSched s, uint32_t *ends) {
+  __shared__ uint32_t cnt[kScanBlock * kScanPer];
+  __shared__ uint32_t wsum[kScanBlock / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t n = b.n;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < n; base += kScanBlock * kScanPer) {
+    const uint32_t m = min(n - base, (uint32_t)(kScanBlock * kScanPer));
+    for (uint32_t k = tid; k < m; k += kScanBlock)
+      cnt[k] = (uint32_t)piece_count(b.dst[base + k], b.size[base + k], s.chunk, s.wgs);
+    __syncthreads();
+    const uint32_t k0 = min(tid * kScanPer, m), k1 = min(k0 + kScanPer, m);
+    uint32_t sum = 0;
+    for (uint32_t k = k0; k < k1; k++) sum += cnt[k];
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t t = __shfl_up(inc, o, 64);
+      if (lane >= (uint32_t)o) inc += t;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t run = carry + inc - sum, round = 0;
+    for (uint32_t w = 0; w < kScanBlock / 64; w++) {
+      if (w < wave) run += wsum[w];
+      round += wsum[w];
+    }
+    for (uint32_t k = k0; k < k1; k++) {
+      run += cnt[k];
+      cnt[k] = run;
+    }
+    carry += round;
+    __syncthreads();
+    for (uint32_t k = tid; k < m; k += kScanBlock) ends[base + k] = cnt[k];
+    __syncthreads();  // cnt and wsum are reused by the next round
+  }
+}
+
+// Copy against a scanned table in device memory: wavefront w of the W in
+// the grid takes pieces [total * w / W, total * (w + 1) / W), searches once
+// for the request of its first piece and walks forward from there (every
+// request has at least one piece, so the walk advances one request at a
+// time).  The descriptor of the next request is loaded before the current
+// piece is copied.
+__global__ __launch_bounds__(kCopyBlock) void copy_kernel_mem(DevBatch b, DevSched s,
+                                                              const uint32_t *ends_in) {
+  const GLOBAL uint32_t *ends = (const GLOBAL uint32_t *)ends_in;
+  constexpr uint32_t kWaves = kCopyBlock / 64;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t n = b.n;
+  const uint64_t total = ends[n - 1];
+  const uint64_t W = (uint64_t)gridDim.x * kWaves;
+  const uint64_t gw = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  uint32_t q = (uint32_t)(total * gw / W);
+  const uint32_t q1 = (uint32_t)(total * (gw + 1) / W);
+  if (q >= q1) return;
+  uint32_t i = __builtin_amdgcn_readfirstlane(find_piece_owner(ends, n, q, lane));
+  uint32_t start = i ? ends[i - 1] : 0u, end = ends[i];
+  uint64_t dst = b.dst[i], src = b.src[i], size = b.size[i];
+  for (; q < q1; q++) {
+    // piece q + 1 in this range belongs to request i + 1 (< n, since
+    // q + 1 < total): load its descriptor before copying piece q
+    const bool next = q + 1 < q1 && q + 1 >= end;
+    uint32_t nend = 0;
+    uint64_t ndst = 0, nsrc = 0, nsize = 0;
+    if (next) {
+      nend = ends[i + 1];
+      ndst = b.dst[i + 1];
+      nsrc = b.src[i + 1];
+      nsize = b.size[i + 1];
+    }
+    copy_piece(dst, src, size, piece_len(dst, size, s.chunk, s.wgs), q - start, s.unroll, lane);
+    if (next) {
+      i++;
+      start = end;
+      end = nend;
+      dst = ndst;
+      src = nsrc;
+      size = nsize;
+    }
   }
 }
 
 hipError_t launch_copy(const DevBatch &b, DevSched s, uint32_t grid, hipStream_t stream) {
   if (b.n > kMaxLdsDescs || grid == 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(kCopyBlock), 0, stream, b, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const DevBatch &b, DevSched s, uint32_t *ends, hipStream_t stream) {
+  if (b.n == 0 || !ends) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanBlock), 0, stream, b, s, ends);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_mem(const DevBatch &b, DevSched s, const uint32_t *ends, uint32_t grid,
+                           hipStream_t stream) {
+  if (b.n == 0 || !ends || grid == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_kernel_mem, dim3(grid), dim3(kCopyBlock), 0, stream, b, s, ends);
   return hipGetLastError();
 }
 

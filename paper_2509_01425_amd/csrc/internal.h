@@ -8,7 +8,8 @@
 namespace hicr {
 
 constexpr int kCopyBlock = 256;         // threads per copy workgroup (4 waves)
-constexpr uint32_t kMaxLdsDescs = 4096; // requests per launch (16 KiB LDS piece table)
+constexpr int kScanBlock = 1024;        // threads of the one scan workgroup
+constexpr uint32_t kMaxLdsDescs = 4096; // requests scanned into LDS by every copy workgroup
 constexpr uint32_t kLineBytes = 128;    // interior piece boundaries are line aligned
 constexpr uint32_t kMinSplit = 1024;    // never split a request below 1 KiB pieces
 
@@ -27,6 +28,14 @@ struct DevSched {
   uint32_t chunk, wgs, unroll, cls;
 };
 
+// ceil(a / b), in 32-bit arithmetic when both fit (a 64-bit division is
+// several times longer on the GPU).
+__host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) {
+  if (a == 0) return 0;
+  if (((a | b) >> 32) == 0) return 1 + ((uint32_t)a - 1) / (uint32_t)b;
+  return 1 + (a - 1) / b;
+}
+
 // Piece length for one request under (chunk, wgs): pieces start at line
 // boundaries of the destination (except the first), so a piece never shares
 // a 16-byte store with its neighbour inside one request.
@@ -35,7 +44,7 @@ __host__ __device__ inline uint64_t piece_len(uint64_t dst, uint64_t size, uint3
   uint64_t span = dst + size - (dst & ~(uint64_t)(kLineBytes - 1));
   uint64_t L = chunk;
   if (wgs > 1 && span < (uint64_t)wgs * chunk) {
-    uint64_t per = (span + wgs - 1) / wgs;
+    uint64_t per = div_up(span, wgs);
     per = (per + kLineBytes - 1) & ~(uint64_t)(kLineBytes - 1);
     if (per < kMinSplit) per = kMinSplit;
     if (per < L) L = per;
@@ -47,12 +56,18 @@ __host__ __device__ inline uint64_t piece_count(uint64_t dst, uint64_t size, uin
                                                 uint32_t wgs) {
   if (size == 0) return 1;  // a zero-byte request still completes (and counts) once
   uint64_t span = dst + size - (dst & ~(uint64_t)(kLineBytes - 1));
-  uint64_t L = piece_len(dst, size, chunk, wgs);
-  return (span + L - 1) / L;
+  return div_up(span, piece_len(dst, size, chunk, wgs));
 }
 
-// Launch the fused copy kernel over one sub-batch (n <= kMaxLdsDescs).
+// Launch the fused copy kernel over one sub-batch (n <= kMaxLdsDescs), piece
+// table scanned in LDS by every workgroup.
 hipError_t launch_copy(const DevBatch &b, DevSched s, uint32_t grid, hipStream_t stream);
+// Scan the pieces of a batch (n >= 1, fewer than 2^31 pieces) into ends[0, n)
+// (inclusive prefix, device memory) with one workgroup.
+hipError_t launch_scan(const DevBatch &b, DevSched s, uint32_t *ends, hipStream_t stream);
+// Launch the copy kernel over a batch whose table launch_scan has written.
+hipError_t launch_copy_mem(const DevBatch &b, DevSched s, const uint32_t *ends, uint32_t grid,
+                           hipStream_t stream);
 // Raise the slot counters of n requests (slots[i] = dst | src << 32); queued
 // after the copy launches of the same requests on the same stream.
 hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters,

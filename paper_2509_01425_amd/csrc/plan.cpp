@@ -1,9 +1,10 @@
 // plan.cpp -- persistent memcpy batches replayed from a HIP graph.
 //
 // A plan is a batch of memcpy requests (HiCR Sec. 3.1.4) that a caller
-// repeats unchanged.  Validation, address resolution and the upload happen
-// once.  A replay queues the fused copy launches (one per sub-batch of at
-// most 4,096 requests) and the counter kernel again, either directly or --
+// repeats unchanged.  Validation, address resolution, the upload, the split
+// into copy launches and (for batches of more than 4,096 requests) the scan
+// of the piece table happen once.  A replay queues the fused copy launches
+// and the counter kernel again, either directly or --
 // HICR_PLAN_GRAPH -- as one hipGraphLaunch of those launches captured from a
 // private stream at creation.  The graph holds kernel nodes only; nothing in
 // it needs clearing between replays.  (Measured on gfx950 with ROCm 7: a
@@ -22,10 +23,10 @@ using namespace hicr;
 struct hicr_plan_s {
   hicr_ctx c = nullptr;
   uint64_t n = 0;
-  void *d = nullptr;          // device SoA {dst, src, size, slot pair}, 32 B per request
+  void *d = nullptr;          // device SoA {dst, src, size, slot pair} + piece table, 36 B per request
+  std::vector<Seg> segs;      // copy launches of one replay
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;  // HICR_PLAN_GRAPH
-  std::vector<uint64_t> h;        // host copy of the packed requests (direct replay)
   DevSched ds{};
   hipEvent_t ev = nullptr;    // end of the last replay
   hipStream_t last = nullptr; // stream of the last replay
@@ -128,9 +129,16 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
 
   std::vector<uint64_t> h(4 * std::max<uint64_t>(n, 1));
   pack_batch(c, d, n, h.data());
+  DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
+  p->ds = ds;
+  rc = split_batch(c, h.data(), h.data() + 2 * n, n, ds, p->segs);
+  if (rc != HICR_OK) {
+    free_plan(p);
+    return rc;
+  }
   hipStream_t cs = nullptr;
   hipError_t e = hipEventCreateWithFlags(&p->ev, hipEventDisableTiming);
-  if (e == hipSuccess && n) e = hipMalloc(&p->d, n * 32);
+  if (e == hipSuccess && n) e = hipMalloc(&p->d, batch_bytes(n));
   if (e == hipSuccess && n) e = hipMemcpy(p->d, h.data(), n * 32, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -139,12 +147,22 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
     return hip_fail(c, e, "allocating a plan");
   }
   const uint64_t *dd = static_cast<const uint64_t *>(p->d);
-  DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
-  p->ds = ds;
+  uint32_t *ends = n ? batch_ends(p->d, n) : nullptr;
+  // the piece table is scanned once; every replay reads it
+  rc = launch_scans(c, dd, n, p->segs, ds, ends, cs);
+  if (rc == HICR_OK) {
+    e = hipStreamSynchronize(cs);
+    if (e != hipSuccess) rc = hip_fail(c, e, "scanning a plan");
+  }
+  if (rc != HICR_OK) {
+    (void)hipStreamDestroy(cs);
+    free_plan(p);
+    return rc;
+  }
   if (flags & HICR_PLAN_GRAPH) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-      rc = launch_batch(c, dd, n, h.data(), h.data() + 2 * n, ds, c->d_counters, cs);
+      rc = launch_copies(c, dd, n, p->segs, ds, ends, c->d_counters, cs);
       hipGraph_t graph = nullptr;
       hipError_t e2 = hipStreamEndCapture(cs, &graph);
       p->graph = graph;
@@ -156,8 +174,6 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
     } else {
       rc = hip_fail(c, e, "capturing a plan");
     }
-  } else {
-    p->h.swap(h);
   }
   (void)hipStreamDestroy(cs);
   if (rc != HICR_OK) {
@@ -181,8 +197,7 @@ int hicr_plan_launch(hicr_plan p, void *stream) {
     e = hipGraphLaunch(p->exec, s);
   } else if (e == hipSuccess && p->n) {
     const uint64_t *dd = static_cast<const uint64_t *>(p->d);
-    int rc = launch_batch(c, dd, p->n, p->h.data(), p->h.data() + 2 * p->n, p->ds, c->d_counters,
-                          s);
+    int rc = launch_copies(c, dd, p->n, p->segs, p->ds, batch_ends(p->d, p->n), c->d_counters, s);
     if (rc != HICR_OK) return rc;
   }
   if (e == hipSuccess) e = hipEventRecord(p->ev, s);

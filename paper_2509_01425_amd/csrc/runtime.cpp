@@ -126,7 +126,7 @@ static int ensure_capacity(hicr_ctx c, Sub &s, uint64_t n) {
   s.cap = 0;
   hipError_t e = hipHostMalloc(&s.h, cap * 32, hipHostMallocDefault);
   if (e != hipSuccess) return fail(c, HICR_ENOMEM, "pinned staging of %llu requests", (unsigned long long)cap);
-  e = hipMalloc(&s.d, cap * 32);
+  e = hipMalloc(&s.d, batch_bytes(cap));
   if (e != hipSuccess) return fail(c, HICR_ENOMEM, "device batch buffer of %llu requests", (unsigned long long)cap);
   s.cap = cap;
   return HICR_OK;
@@ -152,38 +152,65 @@ int default_grid_per_cu(const DevSched &ds) {
   return ds.unroll >= 4 ? 1 : 2;
 }
 
-int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
-                 const uint64_t *hz, DevSched ds, uint64_t *counters, hipStream_t stream) {
-  const int per_cu_class = c->grid_per_cu > 0 ? c->grid_per_cu : default_grid_per_cu(ds);
+int split_batch(hicr_ctx c, const uint64_t *hd, const uint64_t *hz, uint64_t n, const DevSched &ds,
+                std::vector<Seg> &out) {
+  out.clear();
+  const bool lds = n <= kMaxLdsDescs;
   uint64_t i0 = 0;
   while (i0 < n) {
     uint64_t i1 = i0, pieces = 0, bytes = 0;
-    while (i1 < n && i1 - i0 < kMaxLdsDescs) {
+    while (i1 < n && (!lds || i1 - i0 < kMaxLdsDescs)) {
       uint64_t p = piece_count(hd[i1], hz[i1], ds.chunk, ds.wgs);
       if (i1 > i0 && pieces + p >= (1ull << 31)) break;
       pieces += p;
       bytes += hz[i1];
       i1++;
     }
-    // Pieces of a few KiB are latency-bound (search, head and tail bytes, one
-    // or two vector rounds): when the average piece is under 16 KiB, four
-    // groups per CU let every wavefront start on its own piece at once.
-    int per_cu = per_cu_class;
-    if (c->grid_per_cu == 0 && bytes < pieces * (16u << 10)) per_cu = std::max(per_cu, 4);
-    per_cu = std::min(per_cu, c->occ);
-    const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)per_cu;
     if (pieces >= (1ull << 31))
       return fail(c, HICR_EINVAL, "request %llu needs more than 2^31 pieces",
                   (unsigned long long)i0);
-    DevBatch b{dd + i0, dd + n + i0, dd + 2 * n + i0, dd + 3 * n + i0, (uint32_t)(i1 - i0)};
-    // every wavefront of a workgroup copies its own piece
-    const uint64_t want = (pieces + kCopyBlock / 64 - 1) / (kCopyBlock / 64);
-    uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), cap_grid);
-    hipError_t e = launch_copy(b, ds, grid, stream);
-    if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
+    out.push_back(Seg{i0, i1, pieces, bytes, lds});
     i0 = i1;
   }
-  if (counters) {
+  return HICR_OK;
+}
+
+static DevBatch seg_batch(const uint64_t *dd, uint64_t n, const Seg &g) {
+  return DevBatch{dd + g.i0, dd + n + g.i0, dd + 2 * n + g.i0, dd + 3 * n + g.i0,
+                  (uint32_t)(g.i1 - g.i0)};
+}
+
+int launch_scans(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
+                 DevSched ds, uint32_t *ends, hipStream_t stream) {
+  for (const Seg &g : segs) {
+    if (g.lds) continue;
+    hipError_t e = launch_scan(seg_batch(dd, n, g), ds, ends + g.i0, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launching the scan kernel");
+  }
+  return HICR_OK;
+}
+
+int launch_copies(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
+                  DevSched ds, const uint32_t *ends, uint64_t *counters, hipStream_t stream) {
+  const int per_cu_class = c->grid_per_cu > 0 ? c->grid_per_cu : default_grid_per_cu(ds);
+  for (const Seg &g : segs) {
+    // A launch over a scanned table whose pieces average under 16 KiB (a
+    // halo exchange's rows) is latency-bound: four groups per CU measured
+    // 1.45x faster than one at unroll 4.  (With an LDS table every group
+    // re-scans the batch, so more groups cost more there.)
+    int per_cu = per_cu_class;
+    if (c->grid_per_cu == 0 && !g.lds && g.bytes < g.pieces * (16u << 10))
+      per_cu = std::max(per_cu, 4);
+    per_cu = std::min(per_cu, c->occ);
+    const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)per_cu;
+    // every wavefront of a workgroup copies its own pieces
+    const uint64_t want = (g.pieces + kCopyBlock / 64 - 1) / (kCopyBlock / 64);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), cap_grid);
+    hipError_t e = g.lds ? launch_copy(seg_batch(dd, n, g), ds, grid, stream)
+                         : launch_copy_mem(seg_batch(dd, n, g), ds, ends + g.i0, grid, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
+  }
+  if (counters && n) {
     hipError_t e = launch_count(dd + 3 * n, n, counters, stream);
     if (e != hipSuccess) return hip_fail(c, e, "launching the counter kernel");
   }
@@ -225,11 +252,15 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
   const uint64_t *dd = static_cast<const uint64_t *>(s.d);
   DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
   uint64_t *counters = (opt && opt->no_count) ? nullptr : c->d_counters;
+  rc = split_batch(c, h, h + 2 * n, n, ds, c->segs);
+  if (rc != HICR_OK) return rc;
   if (opt && opt->t0) {
     e = hipEventRecord(opt->t0, stream);
     if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
   }
-  rc = launch_batch(c, dd, n, h, h + 2 * n, ds, counters, stream);
+  uint32_t *ends = batch_ends(s.d, n);
+  rc = launch_scans(c, dd, n, c->segs, ds, ends, stream);
+  if (rc == HICR_OK) rc = launch_copies(c, dd, n, c->segs, ds, ends, counters, stream);
   if (rc != HICR_OK) return rc;
   if (opt && opt->t1) {
     e = hipEventRecord(opt->t1, stream);

@@ -35,10 +35,19 @@ struct Sub {
   bool inflight = false;
 };
 
+// One copy launch of a batch: requests [i0, i1) with `pieces` pieces and
+// `bytes` bytes; `lds` when every workgroup scans the piece table into LDS
+// itself, otherwise the launch reads a table that scan_kernel wrote
+// (ends[i0, i1)).
+struct Seg {
+  uint64_t i0, i1, pieces, bytes;
+  bool lds;
+};
+
 // Extra controls of one submission (autotuner).
 struct SubmitOpts {
   bool no_count = false;     // do not raise slot counters
-  hipEvent_t t0 = nullptr;   // recorded just before the first copy launch
+  hipEvent_t t0 = nullptr;   // recorded just before the first scan or copy launch
   hipEvent_t t1 = nullptr;   // recorded just after the last copy launch
 };
 
@@ -68,7 +77,7 @@ struct hicr_ctx_s {
   hipStream_t aux = nullptr;  // counter reads, never waits on `stream`
   int n_cu = 1;
   int occ = 1;       // copy workgroups per CU that fit
-  int grid_per_cu = 0;  // copy workgroups per CU launched (0: all that fit)
+  int grid_per_cu = 0;  // copy workgroups per CU launched (0: per-schedule default)
   uint32_t pair_mask = HICR_PAIRS_ALL;  // memory-space pairs memcpy accepts
   std::vector<hicr::Slot> slots;
   uint64_t *d_counters = nullptr;  // [slot] = {sent, recv}
@@ -76,6 +85,7 @@ struct hicr_ctx_s {
   uint64_t *h_read = nullptr;  // pinned read-back buffer
   hicr::Sub subs[hicr::kNumSubs];
   int next_sub = 0;
+  std::vector<hicr::Seg> segs;  // launches of the submission being queued
   std::vector<hicr_desc> pending;
   hicr_sched def_sched{};
   hicr::SchedState *sched = nullptr;
@@ -108,10 +118,24 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
 int flush_pending(hicr_ctx c);
 // Resolve requests to the structure of arrays {dst, src, size, slot pair}.
 void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h);
-// Launch the copy kernel over an uploaded batch, one launch per sub-batch of
-// at most kMaxLdsDescs requests (hd/hz: host copies of dst and size).
-int launch_batch(hicr_ctx c, const uint64_t *dd, uint64_t n, const uint64_t *hd,
-                 const uint64_t *hz, DevSched ds, uint64_t *counters, hipStream_t stream);
+// Split an n-request batch into copy launches (hd/hz: host copies of dst and
+// size): one LDS-scanned launch up to kMaxLdsDescs requests, otherwise
+// launches over a scanned table; every launch under 2^31 pieces.
+int split_batch(hicr_ctx c, const uint64_t *hd, const uint64_t *hz, uint64_t n, const DevSched &ds,
+                std::vector<Seg> &out);
+// Queue the scan kernel for every launch that reads a table (ends: n
+// entries of device memory beside the uploaded batch dd).
+int launch_scans(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
+                 DevSched ds, uint32_t *ends, hipStream_t stream);
+// Queue the copy launches, then (counters != null) the counter kernel.
+int launch_copies(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
+                  DevSched ds, const uint32_t *ends, uint64_t *counters, hipStream_t stream);
+// Bytes of device memory an uploaded batch of n requests takes: the packed
+// requests (32 B each) and the piece table (4 B each).
+inline uint64_t batch_bytes(uint64_t n) { return n * 36; }
+inline uint32_t *batch_ends(void *d, uint64_t n) {
+  return reinterpret_cast<uint32_t *>(static_cast<char *>(d) + n * 32);
+}
 
 // Persistent batch plans (plan.cpp).
 int wait_plans(hicr_ctx c);

@@ -178,6 +178,63 @@ def test_many_requests_split_launches(env):
     assert H.hicr_slot_counters(ctx, b) == (H.OK, n, 0)
 
 
+def test_large_batch_scanned_table_all_classes(env):
+    """8,193 requests of 0..256 KiB at odd offsets (more than 4,096, so the
+    piece table is scanned once into device memory and every wavefront walks
+    a range of it), under all 12 classes and as direct and graph plans."""
+    torch, H, wd, ctx = env
+    g = np.random.default_rng(5)
+    n = 8193
+    sz = np.floor(np.exp(g.uniform(0, np.log(256 << 10), n))).astype(np.int64)
+    sz[g.integers(0, n, 50)] = 0
+    gap = g.integers(0, 200, n)
+    dst = np.concatenate([[0], np.cumsum(sz + gap)[:-1]]) + 7
+    src_base = int(dst[-1] + sz[-1] + 4096)
+    src = src_base + np.concatenate([[0], np.cumsum(sz + gap[::-1])[:-1]]) + 11
+    pool_len = int(src[-1] + sz[-1] + 64)
+    seed = 21
+    _say("scanned table", n, pool_len)
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    rc, a = H.hicr_slot_register(ctx, pool.data_ptr(), src_base, H.MEM_HBM)
+    rc2, b = H.hicr_slot_register(ctx, pool.data_ptr() + src_base, pool_len - src_base, H.MEM_HBM)
+    assert rc == rc2 == H.OK
+    d = np.zeros(n, dtype=H.DESC_DTYPE)
+    d["dst_slot"], d["src_slot"] = a, b
+    d["dst_off"], d["src_off"], d["size"] = dst, src - src_base, sz
+    host = content(seed, 0, pool_len)
+    oc = oracle.Ctx()
+    oa = oc.register(host, offset=0, size=src_base)[1]
+    ob = oc.register(host, offset=src_base, size=pool_len - src_base)[1]
+    od = d.copy()
+    od["dst_slot"], od["src_slot"] = oa, ob
+    assert oc.memcpy_batch(od)[0] == oracle.OK
+    runs = 0
+    for cls in range(12):
+        _say("scanned table class", cls)
+        wd.fill(pool.data_ptr(), pool_len, seed)
+        torch.cuda.synchronize()
+        assert H.hicr_memcpy_batch(ctx, d, H.hicr_sched_class(cls)[1])[0] == H.OK
+        assert H.hicr_fence(ctx) == H.OK
+        runs += 1
+        assert np.array_equal(pool.cpu().numpy(), host), cls
+    for flags in (0, H.PLAN_GRAPH):
+        _say("scanned table plan flags", flags)
+        rc, plan, _ = H.hicr_plan_create(ctx, d, H.hicr_sched_class(2)[1], flags)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        for _ in range(2):
+            wd.fill(pool.data_ptr(), pool_len, seed)
+            torch.cuda.synchronize()
+            assert H.hicr_plan_launch(plan) == H.OK
+            assert H.hicr_fence(ctx) == H.OK
+            runs += 1
+            assert np.array_equal(pool.cpu().numpy(), host), flags
+        assert H.hicr_plan_destroy(plan) == H.OK
+    assert H.hicr_slot_counters(ctx, a) == (H.OK, 0, runs * n)
+    assert H.hicr_slot_counters(ctx, b) == (H.OK, runs * n, 0)
+    assert H.hicr_slot_deregister(ctx, a) == H.OK
+    assert H.hicr_slot_deregister(ctx, b) == H.OK
+
+
 def test_single_memcpy_broadcast_and_fence_slot(env):
     """One message copied to many destinations with single memcpy calls and
     one fence (the paper's broadcast example, on one memory space)."""
