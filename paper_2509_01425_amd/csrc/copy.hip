@@ -6,14 +6,15 @@
 //      prefix scan of the pieces per request.  A batch of at most 4,096
 //      requests is scanned by every workgroup into LDS (wavefront scans with
 //      __shfl_up, then a cross-wave carry); a larger one is scanned once, by
-//      one workgroup of scan_kernel staging 8,192 requests at a time in LDS,
-//      into a table in device memory that every copy workgroup then reads;
+//      scan_kernel, one workgroup per tile of 4,096 requests (the tile's
+//      prefix staged in LDS, written to device memory with the tile total),
+//      and every copy workgroup scans only the tile totals into LDS;
 //   2. every wavefront is an independent worker.  Against an LDS table,
 //      wave w of workgroup g takes pieces 4g + w, 4g + w + 4G, ... and finds
 //      each piece's request by a 64-ary ballot search (two ballots for 4,096
-//      requests).  Against a device-memory table, every wavefront takes one
-//      contiguous range of pieces, searches once for its first request and
-//      then walks forward request by request;
+//      requests).  Against the tiled table, every wavefront takes one
+//      contiguous range of pieces, searches once for its first request (tile,
+//      then request inside the tile) and walks forward request by request;
 //   3. a piece is copied by its wave with 16-byte destination-aligned vector
 //      stores and 16-byte loads at whatever alignment the source has (the HSA
 //      ABI runs gfx950 in unaligned-access mode), `unroll` vectors in flight
@@ -136,20 +137,17 @@ __device__ __forceinline__ void copy_piece(uint64_t dst, uint64_t src, uint64_t 
   if (lo < hi) copy_range(lo, hi, src + (lo - dst), unroll, lane);
 }
 
-__global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s) {
-  __shared__ uint32_t ends[kMaxLdsDescs];
-  __shared__ uint32_t wsum[kCopyBlock / 64];
+// Inclusive prefix scan, in place, of v[0, m) in LDS by a whole workgroup
+// of B threads: every thread sums a run of consecutive entries, the run sums
+// are scanned per wavefront with __shfl_up, wsum[] carries across
+// wavefronts, and every thread rewrites its run.  Ends with a barrier.
+template <int B>
+__device__ __forceinline__ void block_scan(uint32_t *v, uint32_t m, uint32_t *wsum) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t n = b.n;
-
-  // 1. pieces per request, then an inclusive block scan in LDS
-  for (uint32_t i = tid; i < n; i += kCopyBlock)
-    ends[i] = (uint32_t)piece_count(b.dst[i], b.size[i], s.chunk, s.wgs);
-  __syncthreads();
-  const uint32_t per = (n + kCopyBlock - 1) / kCopyBlock;
-  const uint32_t k0 = min(tid * per, n), k1 = min(k0 + per, n);
+  const uint32_t per = (m + B - 1) / B;
+  const uint32_t k0 = min(tid * per, m), k1 = min(k0 + per, m);
   uint32_t sum = 0;
-  for (uint32_t k = k0; k < k1; k++) sum += ends[k];
+  for (uint32_t k = k0; k < k1; k++) sum += v[k];
   uint32_t inc = sum;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -161,10 +159,23 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
   uint32_t run = inc - sum;
   for (uint32_t w = 0; w < wave; w++) run += wsum[w];
   for (uint32_t k = k0; k < k1; k++) {
-    run += ends[k];
-    ends[k] = run;
+    run += v[k];
+    v[k] = run;
   }
   __syncthreads();
+}
+
+__global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s) {
+  __shared__ uint32_t ends[kMaxLdsDescs];
+  __shared__ uint32_t wsum[kCopyBlock / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t n = b.n;
+
+  // 1. pieces per request, then an inclusive block scan in LDS
+  for (uint32_t i = tid; i < n; i += kCopyBlock)
+    ends[i] = (uint32_t)piece_count(b.dst[i], b.size[i], s.chunk, s.wgs);
+  __syncthreads();
+  block_scan<kCopyBlock>(ends, n, wsum);
   const uint32_t total = n ? ends[n - 1] : 0;
 
   // 2-3. persistent loop over pieces, one wavefront per piece
@@ -179,78 +190,78 @@ __global__ __launch_bounds__(kCopyBlock) void copy_kernel(DevBatch b, DevSched s
   }
 }
 
-// Pieces per request and their inclusive prefix scan for a whole batch, by
-// one workgroup: rounds of kScanBlock x kScanPer requests, counted coalesced
-// into LDS, scanned kScanPer consecutive entries per thread, wavefront scans
-// of the per-thread sums, a cross-wave carry, and a carry across rounds.
-constexpr int kScanPer = 8;
-__global__ __launch_bounds__(kScanBlock) void scan_kernel(DevBatch b, DevSched s, uint32_t *ends) {
-  __shared__ uint32_t cnt[kScanBlock * kScanPer];
+// Table of a large batch, one workgroup per tile of kTile requests: the
+// tile's piece counts are loaded (all of a thread's loads in flight at
+// once), counted into LDS, scanned there, and written out as the tile's
+// inclusive prefix (relative to the tile's first piece) with the tile's
+// total in tile_tot[tile].
+__global__ __launch_bounds__(kScanBlock) void scan_kernel(DevBatch b, DevSched s, uint32_t *ends,
+                                                          uint32_t *tile_tot) {
+  constexpr int kPer = kTile / kScanBlock;
+  __shared__ uint32_t cnt[kTile];
   __shared__ uint32_t wsum[kScanBlock / 64];
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t n = b.n;
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < n; base += kScanBlock * kScanPer) {
-    const uint32_t m = min(n - base, (uint32_t)(kScanBlock * kScanPer));
-    for (uint32_t k = tid; k < m; k += kScanBlock)
-      cnt[k] = (uint32_t)piece_count(b.dst[base + k], b.size[base + k], s.chunk, s.wgs);
-    __syncthreads();
-    const uint32_t k0 = min(tid * kScanPer, m), k1 = min(k0 + kScanPer, m);
-    uint32_t sum = 0;
-    for (uint32_t k = k0; k < k1; k++) sum += cnt[k];
-    uint32_t inc = sum;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t i0 = blockIdx.x * kTile, m = min(b.n - i0, kTile);
+  uint64_t dv[kPer], zv[kPer];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      uint32_t t = __shfl_up(inc, o, 64);
-      if (lane >= (uint32_t)o) inc += t;
-    }
-    if (lane == 63) wsum[wave] = inc;
-    __syncthreads();
-    uint32_t run = carry + inc - sum, round = 0;
-    for (uint32_t w = 0; w < kScanBlock / 64; w++) {
-      if (w < wave) run += wsum[w];
-      round += wsum[w];
-    }
-    for (uint32_t k = k0; k < k1; k++) {
-      run += cnt[k];
-      cnt[k] = run;
-    }
-    carry += round;
-    __syncthreads();
-    for (uint32_t k = tid; k < m; k += kScanBlock) ends[base + k] = cnt[k];
-    __syncthreads();  // cnt and wsum are reused by the next round
+  for (int r = 0; r < kPer; r++) {
+    const uint32_t k = tid + r * kScanBlock;
+    dv[r] = k < m ? b.dst[i0 + k] : 0;
+    zv[r] = k < m ? b.size[i0 + k] : 0;
   }
+#pragma unroll
+  for (int r = 0; r < kPer; r++) {
+    const uint32_t k = tid + r * kScanBlock;
+    if (k < m) cnt[k] = (uint32_t)piece_count(dv[r], zv[r], s.chunk, s.wgs);
+  }
+  __syncthreads();
+  block_scan<kScanBlock>(cnt, m, wsum);
+  for (uint32_t k = tid; k < m; k += kScanBlock) ends[i0 + k] = cnt[k];
+  if (tid == 0) tile_tot[blockIdx.x] = cnt[m - 1];
 }
 
-// Copy against a scanned table in device memory: wavefront w of the W in
-// the grid takes pieces [total * w / W, total * (w + 1) / W), searches once
-// for the request of its first piece and walks forward from there (every
-// request has at least one piece, so the walk advances one request at a
-// time).  The descriptor of the next request is loaded before the current
-// piece is copied.
+// Copy against the tiled table in device memory.  Every workgroup first
+// scans the tile totals into LDS (at most kMaxTiles of them), so piece q's
+// global index is tile_base(tile) + local prefix.  Wavefront w of the W in
+// the grid takes pieces [total * w / W, total * (w + 1) / W), finds the
+// request of its first piece (64-ary search over the tile bases, then over
+// that tile's prefix) and walks forward from there: every request has at
+// least one piece, so the walk advances one request at a time, and the next
+// request's descriptor is loaded before the current piece is copied.
 __global__ __launch_bounds__(kCopyBlock) void copy_kernel_mem(DevBatch b, DevSched s,
-                                                              const uint32_t *ends_in) {
+                                                              const uint32_t *ends_in,
+                                                              const uint32_t *tile_tot) {
+  __shared__ uint32_t tiles[kMaxTiles];
+  __shared__ uint32_t wsum[kCopyBlock / 64];
   const GLOBAL uint32_t *ends = (const GLOBAL uint32_t *)ends_in;
   constexpr uint32_t kWaves = kCopyBlock / 64;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t n = b.n;
-  const uint64_t total = ends[n - 1];
+  const uint32_t n = b.n, nt = (n + kTile - 1) / kTile;
+  for (uint32_t k = threadIdx.x; k < nt; k += kCopyBlock) tiles[k] = tile_tot[k];
+  __syncthreads();
+  block_scan<kCopyBlock>(tiles, nt, wsum);
+  const uint64_t total = tiles[nt - 1];
   const uint64_t W = (uint64_t)gridDim.x * kWaves;
   const uint64_t gw = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
   uint32_t q = (uint32_t)(total * gw / W);
   const uint32_t q1 = (uint32_t)(total * (gw + 1) / W);
   if (q >= q1) return;
-  uint32_t i = __builtin_amdgcn_readfirstlane(find_piece_owner(ends, n, q, lane));
-  uint32_t start = i ? ends[i - 1] : 0u, end = ends[i];
+  const uint32_t t = __builtin_amdgcn_readfirstlane(find_piece_owner(tiles, nt, q, lane));
+  const uint32_t tb = t ? tiles[t - 1] : 0u, t0 = t * kTile;
+  uint32_t i = t0 + __builtin_amdgcn_readfirstlane(
+                        find_piece_owner(ends + t0, min(n - t0, kTile), q - tb, lane));
+  uint32_t start = tb + (i > t0 ? ends[i - 1] : 0u), end = tb + ends[i];
   uint64_t dst = b.dst[i], src = b.src[i], size = b.size[i];
   for (; q < q1; q++) {
     // piece q + 1 in this range belongs to request i + 1 (< n, since
-    // q + 1 < total): load its descriptor before copying piece q
-    const bool next = q + 1 < q1 && q + 1 >= end;
+    // q + 1 < total; checked anyway, so that no table content can send a
+    // wavefront past the batch): load its descriptor before copying piece q
+    const bool next = q + 1 < q1 && q + 1 >= end && i + 1 < n;
     uint32_t nend = 0;
     uint64_t ndst = 0, nsrc = 0, nsize = 0;
     if (next) {
-      nend = ends[i + 1];
+      const uint32_t nt1 = (i + 1) / kTile;
+      nend = (nt1 ? tiles[nt1 - 1] : 0u) + ends[i + 1];
       ndst = b.dst[i + 1];
       nsrc = b.src[i + 1];
       nsize = b.size[i + 1];
@@ -273,16 +284,21 @@ hipError_t launch_copy(const DevBatch &b, DevSched s, uint32_t grid, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const DevBatch &b, DevSched s, uint32_t *ends, hipStream_t stream) {
-  if (b.n == 0 || !ends) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanBlock), 0, stream, b, s, ends);
+hipError_t launch_scan(const DevBatch &b, DevSched s, uint32_t *ends, uint32_t *tile_tot,
+                       hipStream_t stream) {
+  if (b.n == 0 || !ends || !tile_tot || (b.n + kTile - 1) / kTile > kMaxTiles)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_kernel, dim3((b.n + kTile - 1) / kTile), dim3(kScanBlock), 0, stream, b,
+                     s, ends, tile_tot);
   return hipGetLastError();
 }
 
-hipError_t launch_copy_mem(const DevBatch &b, DevSched s, const uint32_t *ends, uint32_t grid,
-                           hipStream_t stream) {
-  if (b.n == 0 || !ends || grid == 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(copy_kernel_mem, dim3(grid), dim3(kCopyBlock), 0, stream, b, s, ends);
+hipError_t launch_copy_mem(const DevBatch &b, DevSched s, const uint32_t *ends,
+                           const uint32_t *tile_tot, uint32_t grid, hipStream_t stream) {
+  if (b.n == 0 || !ends || !tile_tot || grid == 0 || (b.n + kTile - 1) / kTile > kMaxTiles)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_kernel_mem, dim3(grid), dim3(kCopyBlock), 0, stream, b, s, ends,
+                     tile_tot);
   return hipGetLastError();
 }
 

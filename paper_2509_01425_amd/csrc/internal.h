@@ -10,6 +10,8 @@ namespace hicr {
 constexpr int kCopyBlock = 256;         // threads per copy workgroup (4 waves)
 constexpr int kScanBlock = 1024;        // threads of the one scan workgroup
 constexpr uint32_t kMaxLdsDescs = 4096; // requests scanned into LDS by every copy workgroup
+constexpr uint32_t kTile = 4096;        // requests per tile of a scanned table
+constexpr uint32_t kMaxTiles = 4096;    // tiles per launch over a scanned table
 constexpr uint32_t kLineBytes = 128;    // interior piece boundaries are line aligned
 constexpr uint32_t kMinSplit = 1024;    // never split a request below 1 KiB pieces
 
@@ -62,12 +64,14 @@ __host__ __device__ inline uint64_t piece_count(uint64_t dst, uint64_t size, uin
 // Launch the fused copy kernel over one sub-batch (n <= kMaxLdsDescs), piece
 // table scanned in LDS by every workgroup.
 hipError_t launch_copy(const DevBatch &b, DevSched s, uint32_t grid, hipStream_t stream);
-// Scan the pieces of a batch (n >= 1, fewer than 2^31 pieces) into ends[0, n)
-// (inclusive prefix, device memory) with one workgroup.
-hipError_t launch_scan(const DevBatch &b, DevSched s, uint32_t *ends, hipStream_t stream);
+// Scan the pieces of a batch (1 <= n <= kTile * kMaxTiles, fewer than 2^31
+// pieces) into a tiled table: ends[0, n) holds each tile's inclusive prefix
+// relative to the tile, tile_tot[0, ceil(n / kTile)) the tile totals.
+hipError_t launch_scan(const DevBatch &b, DevSched s, uint32_t *ends, uint32_t *tile_tot,
+                       hipStream_t stream);
 // Launch the copy kernel over a batch whose table launch_scan has written.
-hipError_t launch_copy_mem(const DevBatch &b, DevSched s, const uint32_t *ends, uint32_t grid,
-                           hipStream_t stream);
+hipError_t launch_copy_mem(const DevBatch &b, DevSched s, const uint32_t *ends,
+                           const uint32_t *tile_tot, uint32_t grid, hipStream_t stream);
 // Raise the slot counters of n requests (slots[i] = dst | src << 32); queued
 // after the copy launches of the same requests on the same stream.
 hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters,

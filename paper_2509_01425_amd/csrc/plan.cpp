@@ -23,7 +23,7 @@ using namespace hicr;
 struct hicr_plan_s {
   hicr_ctx c = nullptr;
   uint64_t n = 0;
-  void *d = nullptr;          // device SoA {dst, src, size, slot pair} + piece table, 36 B per request
+  void *d = nullptr;          // device SoA {dst, src, size, slot pair} + piece tables, 40 B per request
   std::vector<Seg> segs;      // copy launches of one replay
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;  // HICR_PLAN_GRAPH
@@ -147,9 +147,9 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
     return hip_fail(c, e, "allocating a plan");
   }
   const uint64_t *dd = static_cast<const uint64_t *>(p->d);
-  uint32_t *ends = n ? batch_ends(p->d, n) : nullptr;
-  // the piece table is scanned once; every replay reads it
-  rc = launch_scans(c, dd, n, p->segs, ds, ends, cs);
+  uint32_t *tables = n ? batch_tables(p->d, n) : nullptr;
+  // the piece tables are scanned once; every replay reads them
+  rc = launch_scans(c, dd, n, p->segs, ds, tables, cs);
   if (rc == HICR_OK) {
     e = hipStreamSynchronize(cs);
     if (e != hipSuccess) rc = hip_fail(c, e, "scanning a plan");
@@ -162,7 +162,7 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
   if (flags & HICR_PLAN_GRAPH) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-      rc = launch_copies(c, dd, n, p->segs, ds, ends, c->d_counters, cs);
+      rc = launch_copies(c, dd, n, p->segs, ds, tables, c->d_counters, cs);
       hipGraph_t graph = nullptr;
       hipError_t e2 = hipStreamEndCapture(cs, &graph);
       p->graph = graph;
@@ -197,7 +197,8 @@ int hicr_plan_launch(hicr_plan p, void *stream) {
     e = hipGraphLaunch(p->exec, s);
   } else if (e == hipSuccess && p->n) {
     const uint64_t *dd = static_cast<const uint64_t *>(p->d);
-    int rc = launch_copies(c, dd, p->n, p->segs, p->ds, batch_ends(p->d, p->n), c->d_counters, s);
+    int rc =
+        launch_copies(c, dd, p->n, p->segs, p->ds, batch_tables(p->d, p->n), c->d_counters, s);
     if (rc != HICR_OK) return rc;
   }
   if (e == hipSuccess) e = hipEventRecord(p->ev, s);

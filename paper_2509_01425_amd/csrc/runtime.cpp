@@ -159,7 +159,8 @@ int split_batch(hicr_ctx c, const uint64_t *hd, const uint64_t *hz, uint64_t n, 
   uint64_t i0 = 0;
   while (i0 < n) {
     uint64_t i1 = i0, pieces = 0, bytes = 0;
-    while (i1 < n && (!lds || i1 - i0 < kMaxLdsDescs)) {
+    const uint64_t cap = lds ? kMaxLdsDescs : (uint64_t)kTile * kMaxTiles;
+    while (i1 < n && i1 - i0 < cap) {
       uint64_t p = piece_count(hd[i1], hz[i1], ds.chunk, ds.wgs);
       if (i1 > i0 && pieces + p >= (1ull << 31)) break;
       pieces += p;
@@ -181,17 +182,17 @@ static DevBatch seg_batch(const uint64_t *dd, uint64_t n, const Seg &g) {
 }
 
 int launch_scans(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
-                 DevSched ds, uint32_t *ends, hipStream_t stream) {
+                 DevSched ds, uint32_t *tables, hipStream_t stream) {
   for (const Seg &g : segs) {
     if (g.lds) continue;
-    hipError_t e = launch_scan(seg_batch(dd, n, g), ds, ends + g.i0, stream);
+    hipError_t e = launch_scan(seg_batch(dd, n, g), ds, tables + g.i0, tables + n + g.i0, stream);
     if (e != hipSuccess) return hip_fail(c, e, "launching the scan kernel");
   }
   return HICR_OK;
 }
 
 int launch_copies(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
-                  DevSched ds, const uint32_t *ends, uint64_t *counters, hipStream_t stream) {
+                  DevSched ds, const uint32_t *tables, uint64_t *counters, hipStream_t stream) {
   const int per_cu_class = c->grid_per_cu > 0 ? c->grid_per_cu : default_grid_per_cu(ds);
   for (const Seg &g : segs) {
     // A launch over a scanned table whose pieces average under 16 KiB (a
@@ -207,7 +208,8 @@ int launch_copies(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<
     const uint64_t want = (g.pieces + kCopyBlock / 64 - 1) / (kCopyBlock / 64);
     const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), cap_grid);
     hipError_t e = g.lds ? launch_copy(seg_batch(dd, n, g), ds, grid, stream)
-                         : launch_copy_mem(seg_batch(dd, n, g), ds, ends + g.i0, grid, stream);
+                         : launch_copy_mem(seg_batch(dd, n, g), ds, tables + g.i0,
+                                           tables + n + g.i0, grid, stream);
     if (e != hipSuccess) return hip_fail(c, e, "launching the copy kernel");
   }
   if (counters && n) {
@@ -230,13 +232,6 @@ void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h) {
 // Validate, pack and launch n requests as one submission.
 int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
            hipStream_t stream, uint64_t *bad, const SubmitOpts *opt) {
-  for (uint64_t i = 0; i < n; i++) {
-    int rc = check_desc(c, d[i]);
-    if (rc != HICR_OK) {
-      if (bad) *bad = i;
-      return fail(c, rc, "request %llu rejected", (unsigned long long)i);
-    }
-  }
   if (n == 0) return HICR_OK;
   // Choose the submission buffer (round robin; wait if still in flight).
   Sub &s = c->subs[c->next_sub];
@@ -245,30 +240,46 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
   if (rc != HICR_OK) return rc;
   rc = ensure_capacity(c, s, n);
   if (rc != HICR_OK) return rc;
+  // validate and pack in one pass; nothing is queued unless every request
+  // passes and the batch splits into launches
   uint64_t *h = static_cast<uint64_t *>(s.h);
-  pack_batch(c, d, n, h);
+  uint64_t *hd = h, *hs = h + n, *hz = h + 2 * n, *hp = h + 3 * n;
+  const Slot *sl = c->slots.data();
+  for (uint64_t i = 0; i < n; i++) {
+    const hicr_desc &x = d[i];
+    rc = check_desc(c, x);
+    if (rc != HICR_OK) {
+      if (bad) *bad = i;
+      return fail(c, rc, "request %llu rejected", (unsigned long long)i);
+    }
+    hd[i] = sl[x.dst_slot].base + x.dst_off;
+    hs[i] = sl[x.src_slot].base + x.src_off;
+    hz[i] = x.size;
+    hp[i] = (uint64_t)x.dst_slot | ((uint64_t)x.src_slot << 32);
+  }
+  DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
+  rc = split_batch(c, hd, hz, n, ds, c->segs);
+  if (rc != HICR_OK) return rc;
   hipError_t e = hipMemcpyAsync(s.d, s.h, n * 32, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(c, e, "uploading a batch");
   const uint64_t *dd = static_cast<const uint64_t *>(s.d);
-  DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
   uint64_t *counters = (opt && opt->no_count) ? nullptr : c->d_counters;
-  rc = split_batch(c, h, h + 2 * n, n, ds, c->segs);
-  if (rc != HICR_OK) return rc;
   if (opt && opt->t0) {
     e = hipEventRecord(opt->t0, stream);
     if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
   }
-  uint32_t *ends = batch_ends(s.d, n);
-  rc = launch_scans(c, dd, n, c->segs, ds, ends, stream);
-  if (rc == HICR_OK) rc = launch_copies(c, dd, n, c->segs, ds, ends, counters, stream);
-  if (rc != HICR_OK) return rc;
-  if (opt && opt->t1) {
+  uint32_t *tables = batch_tables(s.d, n);
+  rc = launch_scans(c, dd, n, c->segs, ds, tables, stream);
+  if (rc == HICR_OK) rc = launch_copies(c, dd, n, c->segs, ds, tables, counters, stream);
+  if (rc == HICR_OK && opt && opt->t1) {
     e = hipEventRecord(opt->t1, stream);
-    if (e != hipSuccess) return hip_fail(c, e, "recording a timing event");
+    if (e != hipSuccess) rc = hip_fail(c, e, "recording a timing event");
   }
+  // the staging buffer is in use from the upload on, whatever failed after it
   e = hipEventRecord(s.ev, stream);
+  if (e == hipSuccess) s.inflight = true;
+  if (rc != HICR_OK) return rc;
   if (e != hipSuccess) return hip_fail(c, e, "recording a batch event");
-  s.inflight = true;
   return HICR_OK;
 }
 

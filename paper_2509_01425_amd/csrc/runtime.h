@@ -120,20 +120,23 @@ int flush_pending(hicr_ctx c);
 void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h);
 // Split an n-request batch into copy launches (hd/hz: host copies of dst and
 // size): one LDS-scanned launch up to kMaxLdsDescs requests, otherwise
-// launches over a scanned table; every launch under 2^31 pieces.
+// launches over a scanned table of at most kTile * kMaxTiles requests; every
+// launch under 2^31 pieces.
 int split_batch(hicr_ctx c, const uint64_t *hd, const uint64_t *hz, uint64_t n, const DevSched &ds,
                 std::vector<Seg> &out);
-// Queue the scan kernel for every launch that reads a table (ends: n
-// entries of device memory beside the uploaded batch dd).
+// Queue the scan kernel for every launch that reads a table (tables: the
+// batch_tables() region beside the uploaded batch dd).
 int launch_scans(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
-                 DevSched ds, uint32_t *ends, hipStream_t stream);
+                 DevSched ds, uint32_t *tables, hipStream_t stream);
 // Queue the copy launches, then (counters != null) the counter kernel.
 int launch_copies(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
-                  DevSched ds, const uint32_t *ends, uint64_t *counters, hipStream_t stream);
+                  DevSched ds, const uint32_t *tables, uint64_t *counters, hipStream_t stream);
 // Bytes of device memory an uploaded batch of n requests takes: the packed
-// requests (32 B each) and the piece table (4 B each).
-inline uint64_t batch_bytes(uint64_t n) { return n * 36; }
-inline uint32_t *batch_ends(void *d, uint64_t n) {
+// requests (32 B each), then the piece tables: per-request prefixes (4 B
+// each) and tile totals (a launch over requests [i0, i1) keeps its tiles at
+// entry i0 of an n-entry region; it has fewer tiles than requests).
+inline uint64_t batch_bytes(uint64_t n) { return n * 40; }
+inline uint32_t *batch_tables(void *d, uint64_t n) {
   return reinterpret_cast<uint32_t *>(static_cast<char *>(d) + n * 32);
 }
 
