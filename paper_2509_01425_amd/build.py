@@ -20,10 +20,15 @@ FLAGS = [
 ]
 
 
+# host code built with the host's FMA instructions (its callers check the CPU)
+PER_FILE = {"net_fma.cpp": ["-Xarch_host", "-mfma"]}
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + FLAGS + lang + ["-c", src, "-o", obj]
+    extra = PER_FILE.get(os.path.basename(src), [])
+    cmd = [HIPCC] + FLAGS + extra + lang + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

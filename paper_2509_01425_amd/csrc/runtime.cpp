@@ -156,6 +156,28 @@ int split_batch(hicr_ctx c, const uint64_t *hd, const uint64_t *hz, uint64_t n, 
                 std::vector<Seg> &out) {
   out.clear();
   const bool lds = n <= kMaxLdsDescs;
+  if (!lds) {
+    // A piece spans at least 128 destination bytes except at a request's
+    // ends, so a request has at most size / 128 + 2 pieces.  When that bound
+    // keeps the batch under 2^31 pieces, no per-request count is needed on
+    // the host (the scan kernel counts): launches split by request count
+    // only, and `pieces` holds the lower bound, one per request.
+    uint64_t bytes = 0;
+    for (uint64_t i = 0; i < n; i++) bytes += hz[i];
+    if (bytes < (1ull << 38) && (bytes >> 7) + 2 * n < (1ull << 31)) {
+      const uint64_t cap = (uint64_t)kTile * kMaxTiles;
+      for (uint64_t i0 = 0; i0 < n; i0 += cap) {
+        const uint64_t i1 = std::min(n, i0 + cap);
+        uint64_t b = bytes;
+        if (i0 > 0 || i1 < n) {
+          b = 0;
+          for (uint64_t i = i0; i < i1; i++) b += hz[i];
+        }
+        out.push_back(Seg{i0, i1, i1 - i0, b, false});
+      }
+      return HICR_OK;
+    }
+  }
   uint64_t i0 = 0;
   while (i0 < n) {
     uint64_t i1 = i0, pieces = 0, bytes = 0;
@@ -200,7 +222,8 @@ int launch_copies(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<
     // 1.45x faster than one at unroll 4.  (With an LDS table every group
     // re-scans the batch, so more groups cost more there.)
     int per_cu = per_cu_class;
-    if (c->grid_per_cu == 0 && !g.lds && g.bytes < g.pieces * (16u << 10))
+    if (c->grid_per_cu == 0 && !g.lds &&
+        (ds.chunk <= (16u << 10) || g.bytes < (g.i1 - g.i0) * (16u << 10)))
       per_cu = std::max(per_cu, 4);
     per_cu = std::min(per_cu, c->occ);
     const uint64_t cap_grid = (uint64_t)c->n_cu * (uint64_t)per_cu;

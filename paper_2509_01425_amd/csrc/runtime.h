@@ -35,10 +35,10 @@ struct Sub {
   bool inflight = false;
 };
 
-// One copy launch of a batch: requests [i0, i1) with `pieces` pieces and
-// `bytes` bytes; `lds` when every workgroup scans the piece table into LDS
-// itself, otherwise the launch reads a table that scan_kernel wrote
-// (ends[i0, i1)).
+// One copy launch of a batch: requests [i0, i1) with `bytes` bytes and
+// `pieces` pieces (exact on the LDS path, at least that many on the table
+// path); `lds` when every workgroup scans the piece table into LDS itself,
+// otherwise the launch reads the tables that scan_kernel wrote.
 struct Seg {
   uint64_t i0, i1, pieces, bytes;
   bool lds;
