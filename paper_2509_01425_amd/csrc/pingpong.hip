@@ -67,18 +67,23 @@ __global__ __launch_bounds__(256) void pingpong_kernel(PingPongArgs a) {
   const uint64_t hi = lo + stripe < a.size ? lo + stripe : a.size;
   const uint64_t W = a.W;
   uint64_t deadline = wall_clock64() + a.timeout_ticks;
-  // wait (thread 0 polls) until *ctr >= v; every thread then acquires
+  // wait until *ctr >= v: thread 0 polls and acquires, and the barrier
+  // orders every other wave's later accesses after that acquire (one L2
+  // invalidate per workgroup, not one per wave)
   auto wait = [&](const uint64_t *ctr, uint64_t v) {
     if (t == 0) ok = wait_at_least(ctr, v, deadline, a.err);
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return ok != 0;
   };
-  // every thread releases its copies, then one stripe is counted
+  // the barrier orders every wave's copies before thread 0's release, which
+  // makes them visible device-wide before one stripe is counted (one L2
+  // write-back per workgroup, not one per wave)
   auto signal = [&](uint64_t *ctr) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (t == 0) __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   };
   for (uint32_t k = 0; k < a.reps; k++) {
     if (pinger) {
