@@ -416,12 +416,10 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
         s_stop = stop;
         s_k = (uint32_t)k;
       }
-      // wave 0 acquires the batch; the barrier orders the other waves' reads
-      // after it (one L2 invalidate per unit and batch, not one per wave)
-      if (!stop) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (s_stop) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t k = s_k;
     // message i of the batch: ring and index within it (rings in order from rr)
     if (tid == 0) {
@@ -575,12 +573,10 @@ __device__ void run_lock_team(const PumpArgs &a, uint32_t uid, uint32_t tid) {
       s_end = end;
       s_stop = stop || start >= last;
       s_bad = 0;
-      // records and payload of the round: acquired once, the barrier orders
-      // the other waves' reads after it
-      if (!s_stop) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (s_stop) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // records and payload of the round
     const uint64_t start = s_start, n = s_end - s_start;
     if (tid < n) {
       const uint64_t seq = start + tid;
