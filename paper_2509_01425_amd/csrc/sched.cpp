@@ -26,6 +26,15 @@ struct SchedState {
   MlpBufs bufs{};
   std::vector<std::array<float, kMlpIn>> feats;  // tuned table
   std::vector<uint32_t> cls;
+  // search index of the tuned table (rebuilt after the table changes): the
+  // entries sorted by their distance to the first of three pivots (ties in
+  // table order), with their features, distances to the pivots and table
+  // positions in that order
+  bool idx_dirty = true;
+  std::array<std::array<double, kMlpIn>, 3> piv{};
+  std::vector<std::array<float, kMlpIn>> sf;
+  std::vector<std::array<double, 3>> spd;
+  std::vector<uint32_t> sk;
   // host copy of the network for the per-submission choice (h_params as on
   // the device, h_t transposed for the host forward pass); stale after a
   // device training step until the next learned submission reads it back
@@ -84,29 +93,99 @@ static int ensure_act(hicr_ctx c, SchedState *s, int B) {
   return HICR_OK;
 }
 
-static uint32_t nearest(const SchedState *s, const float *f) {
-  // exact squared distances; a candidate is dropped as soon as a partial sum
-  // (8 bins at a time) already exceeds the best one, which skips most of the
-  // table without changing the answer (first minimum wins, as in a full scan)
-  uint32_t best = 0;
-  float bd = 3.4e38f;
-  for (size_t k = 0; k < s->feats.size(); k++) {
-    const float *g = s->feats[k].data();
-    float d = 0.f;
-    int b = 0;
-    for (; b < kMlpIn; b += 8) {
-      for (int q = b; q < b + 8; q++) {
-        const float x = g[q] - f[q];
-        d += x * x;
-      }
-      if (d >= bd) break;
-    }
-    if (b >= kMlpIn && d < bd) {
-      bd = d;
-      best = s->cls[k];
+static double pivot_dist(const std::array<double, kMlpIn> &p, const float *f) {
+  double d = 0.0;
+  for (int b = 0; b < kMlpIn; b++) d += (f[b] - p[b]) * (f[b] - p[b]);
+  return std::sqrt(d);
+}
+
+// Pivots: the origin, the table's mean feature, and the entry farthest from
+// the mean; entries are ordered by their distance to the origin.
+static void build_index(SchedState *s) {
+  const size_t n = s->feats.size();
+  s->piv[0].fill(0.0);
+  s->piv[1].fill(0.0);
+  for (const auto &g : s->feats)
+    for (int b = 0; b < kMlpIn; b++) s->piv[1][b] += g[b] / (double)n;
+  size_t far = 0;
+  double fd = -1.0;
+  for (size_t k = 0; k < n; k++) {
+    const double d = pivot_dist(s->piv[1], s->feats[k].data());
+    if (d > fd) {
+      fd = d;
+      far = k;
     }
   }
-  return best;
+  for (int b = 0; b < kMlpIn; b++) s->piv[2][b] = s->feats[far][b];
+  std::vector<std::array<double, 3>> pd(n);
+  for (size_t k = 0; k < n; k++)
+    for (int j = 0; j < 3; j++) pd[k][j] = pivot_dist(s->piv[j], s->feats[k].data());
+  s->sk.resize(n);
+  for (size_t k = 0; k < n; k++) s->sk[k] = (uint32_t)k;
+  std::stable_sort(s->sk.begin(), s->sk.end(),
+                   [&](uint32_t x, uint32_t y) { return pd[x][0] < pd[y][0]; });
+  s->sf.resize(n);
+  s->spd.resize(n);
+  for (size_t i = 0; i < n; i++) {
+    s->sf[i] = s->feats[s->sk[i]];
+    s->spd[i] = pd[s->sk[i]];
+  }
+  s->idx_dirty = false;
+}
+
+// Squared distance as the tuned table defines it (fp32, bins in order), or
+// any value above `bound` once a partial sum (8 bins at a time) exceeds it:
+// partial sums of non-negative terms never decrease, so such an entry cannot
+// be nearer than `bound`.
+static float feat_dist(const float *g, const float *f, float bound) {
+  float d = 0.f;
+  for (int b = 0; b < kMlpIn; b += 8) {
+    for (int q = b; q < b + 8; q++) {
+      const float x = g[q] - f[q];
+      d += x * x;
+    }
+    if (d > bound) return d;
+  }
+  return d;
+}
+
+// The class of the first table entry (in table order) at the smallest fp32
+// squared distance from f -- the answer of a full scan.  The scan starts at
+// the entries whose distance to the origin is closest to f's and walks
+// outward; by the triangle inequality an entry e is no nearer than
+// |d(e, p) - d(f, p)| for every pivot p, so a direction stops once that gap
+// exceeds the best distance found, and an entry is skipped when another
+// pivot's gap does.  Gaps are compared with a relative margin of 1e-4, far
+// above the fp32 distance's rounding (~2e-6), so nothing a full scan could
+// pick is pruned.
+static uint32_t nearest(SchedState *s, const float *f) {
+  if (s->idx_dirty) build_index(s);
+  const size_t n = s->feats.size();
+  double q[3];
+  for (int j = 0; j < 3; j++) q[j] = pivot_dist(s->piv[j], f);
+  size_t hi = std::lower_bound(s->spd.begin(), s->spd.end(), q[0],
+                               [](const std::array<double, 3> &e, double v) { return e[0] < v; }) -
+              s->spd.begin();
+  size_t lo = hi;  // candidates [lo, hi) visited; next are lo - 1 and hi
+  float bd = 3.4e38f;
+  uint32_t bk = 0;
+  auto pruned = [&](double gap) { return gap * gap > (double)bd * (1.0 + 1e-4); };
+  for (;;) {
+    const double gl = lo > 0 ? q[0] - s->spd[lo - 1][0] : 1e300;
+    const double gh = hi < n ? s->spd[hi][0] - q[0] : 1e300;
+    const bool take_lo = gl <= gh;
+    const double gap = take_lo ? gl : gh;
+    if (gap >= 1e300 || pruned(gap)) break;  // both directions are done
+    const size_t i = take_lo ? --lo : hi++;
+    if (pruned(std::fabs(s->spd[i][1] - q[1])) || pruned(std::fabs(s->spd[i][2] - q[2]))) continue;
+    const float d = feat_dist(s->sf[i].data(), f, bd);
+    const uint32_t k = s->sk[i];
+    if (d < bd || (d == bd && k < bk)) {
+      bd = d;
+      bk = k;
+    }
+  }
+  return s->cls[bk];
 }
 
 // The network's class for one batch feature: forward pass in fp32 on the
@@ -282,6 +361,7 @@ int hicr_tune_add(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t cls) 
   if (n) batch_features(&descs[0].size, n, sizeof(hicr_desc), f.data());
   s->feats.push_back(f);
   s->cls.push_back(cls);
+  s->idx_dirty = true;
   return HICR_OK;
 }
 
@@ -301,6 +381,7 @@ int hicr_tune_clear(hicr_ctx c) {
   if (c->sched) {
     c->sched->feats.clear();
     c->sched->cls.clear();
+    c->sched->idx_dirty = true;
   }
   return HICR_OK;
 }
