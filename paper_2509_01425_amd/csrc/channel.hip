@@ -46,8 +46,16 @@ __device__ __forceinline__ void st_rel(uint64_t a, uint64_t v) {
 }
 
 // Copy n bytes d <- s with a team of TEAM threads (t = rank in the team):
-// destination-aligned 16-byte stores, source at any alignment, at most 15
-// head and 15 tail bytes one by one.  TEAM >= 64.
+// destination-aligned 16-byte stores, source at any alignment, the at most
+// 15 head and 15 tail bytes one by one.  TEAM >= 64.  The code has no
+// per-lane branch: a lane past the last vector copies the last vector again,
+// and every lane copies one byte (lanes 0-15 the head bytes, 16-31 the tail
+// bytes, a repeated byte once a range is used up, the request's first byte
+// on the other lanes), so repeated stores write equal values and nothing
+// outside the request is touched.  Without lane branches the compiler issues
+// a round's U loads back to back and never waits for an earlier store; a
+// bounds test on every access made it wait for each access in turn (about
+// three memory latencies per round instead of one).
 template <int TEAM, int U>
 __device__ __forceinline__ void team_copy(uint64_t d, uint64_t s, uint64_t n, uint32_t t) {
   if (n == 0) return;
@@ -55,26 +63,30 @@ __device__ __forceinline__ void team_copy(uint64_t d, uint64_t s, uint64_t n, ui
   if (a0 > d + n) a0 = d + n;
   uint64_t a1 = (d + n) & ~(uint64_t)15;
   if (a1 < a0) a1 = a0;
-  if (t < a0 - d) *(GLOBAL unsigned char *)(d + t) = *(const GLOBAL unsigned char *)(s + t);
-  if (t >= 32 && t - 32 < d + n - a1) {
-    uint64_t o = (a1 - d) + (t - 32);
-    *(GLOBAL unsigned char *)(d + o) = *(const GLOBAL unsigned char *)(s + o);
-  }
+  const uint64_t nh = a0 - d, nt = d + n - a1;
+  uint64_t bo = 0;  // this lane's byte, as an offset into the request
+  if (t < 16)
+    bo = nh ? (t < nh ? t : nh - 1) : 0;
+  else if (t < 32)
+    bo = nt ? (a1 - d) + (t - 16 < nt ? t - 16 : nt - 1) : 0;
+  const unsigned char byte = *(const GLOBAL unsigned char *)(s + bo);
   const uint64_t nv = (a1 - a0) >> 4;
-  const uint64_t s16 = s + (a0 - d);
-  for (uint64_t b = 0; b < nv; b += (uint64_t)TEAM * U) {
+  const uint64_t s16 = s + nh;
+  constexpr uint64_t step = (uint64_t)TEAM * U;
+  for (uint64_t b = 0; b < nv; b += step) {
     v4u r[U];
+    uint64_t o[U];
 #pragma unroll
     for (int k = 0; k < U; k++) {
-      uint64_t i = b + t + (uint64_t)k * TEAM;
-      if (i < nv) r[k] = *(const GLOBAL v4u_any *)(s16 + 16 * i);
+      const uint64_t i = b + t + (uint64_t)k * TEAM;
+      o[k] = 16 * (i < nv ? i : nv - 1);
     }
 #pragma unroll
-    for (int k = 0; k < U; k++) {
-      uint64_t i = b + t + (uint64_t)k * TEAM;
-      if (i < nv) *(GLOBAL v4u *)(a0 + 16 * i) = r[k];
-    }
+    for (int k = 0; k < U; k++) r[k] = *(const GLOBAL v4u_any *)(s16 + o[k]);
+#pragma unroll
+    for (int k = 0; k < U; k++) *(GLOBAL v4u *)(a0 + o[k]) = r[k];
   }
+  *(GLOBAL unsigned char *)(d + bo) = byte;
 }
 
 // Payload write / read at ring position pos, split across the ring end.
@@ -156,48 +168,60 @@ __device__ __forceinline__ Seg make_seg(uint64_t d, uint64_t s, uint64_t n) {
   return g;
 }
 
-// All TEAM threads copy nseg segments (held in LDS) as one index space of
-// 16-byte vectors, so a batch of small messages costs about one memory round
-// trip instead of one per message.  Head and tail bytes go one by one.
+// All TEAM threads copy nseg segments (held in LDS, every one non-empty, at
+// most 32) as one index space of 16-byte vectors, so a batch of small
+// messages costs about one memory round trip instead of one per message.
+// Branch-free like team_copy: the head and tail bytes (slot 32 g + j: j < 16
+// head byte j of segment g, else tail byte j - 16) and the vectors are
+// clamped into range, so repeated copies write equal values, and a vector's
+// segment is found by a fixed five-step binary search over the segments'
+// first vectors (v0) instead of a data-dependent loop; the compiler then
+// issues a round's U loads back to back.
 template <int TEAM, int U>
 __device__ void seg_copy(const Seg *sg, uint32_t nseg, uint64_t total_v, uint32_t t) {
-  for (uint32_t x = t; x < nseg * 32; x += TEAM) {
+  if (nseg == 0) return;
+  constexpr int kB = (32 * 32 + TEAM - 1) / TEAM;  // byte slots per thread
+  unsigned char bv[kB];
+  uint64_t bd[kB];
+#pragma unroll
+  for (int q = 0; q < kB; q++) {
+    uint32_t x = t + (uint32_t)q * TEAM;
+    if (x > nseg * 32 - 1) x = nseg * 32 - 1;
     const Seg &g = sg[x >> 5];
     const uint32_t j = x & 31;
-    const uint64_t a1 = g.a0 + 16 * g.nv;
-    if (j < 16) {
-      if (j < g.a0 - g.d)
-        *(GLOBAL unsigned char *)(g.d + j) = *(const GLOBAL unsigned char *)(g.s + j);
-    } else if (j - 16 < g.d + g.n - a1) {
-      const uint64_t o = (a1 - g.d) + (j - 16);
-      *(GLOBAL unsigned char *)(g.d + o) = *(const GLOBAL unsigned char *)(g.s + o);
-    }
+    const uint64_t nh = g.a0 - g.d, a1 = g.a0 + 16 * g.nv, nt = g.d + g.n - a1;
+    uint64_t off;
+    if (j < 16)
+      off = nh ? (j < nh ? j : nh - 1) : 0;
+    else
+      off = nt ? (a1 - g.d) + (j - 16 < nt ? j - 16 : nt - 1) : 0;
+    bv[q] = *(const GLOBAL unsigned char *)(g.s + off);
+    bd[q] = g.d + off;
   }
-  // A thread's vectors only grow (within a round with k, across rounds with
-  // b), so one cursor on the segment of the round's first vector is kept and
-  // stepped forward -- a round usually stays in one segment -- instead of a
-  // search before every load.
-  uint32_t c0 = 0;
+#pragma unroll
+  for (int q = 0; q < kB; q++) *(GLOBAL unsigned char *)(bd[q]) = bv[q];
   for (uint64_t b = 0; b < total_v; b += (uint64_t)TEAM * U) {
-    v4u r[U];
-    uint64_t da[U];
-    uint32_t c = c0;
+    uint64_t sa[U], da[U];
 #pragma unroll
     for (int k = 0; k < U; k++) {
-      const uint64_t v = b + t + (uint64_t)k * TEAM;
-      da[k] = 0;
-      if (v < total_v) {
-        while (c + 1 < nseg && sg[c + 1].v0 <= v) c++;  // last segment with v0 <= v
-        if (k == 0) c0 = c;
-        const Seg &g = sg[c];
-        const uint64_t w = v - g.v0;
-        r[k] = *(const GLOBAL v4u_any *)(g.s + (g.a0 - g.d) + 16 * w);
-        da[k] = g.a0 + 16 * w;
-      }
-    }
+      uint64_t v = b + t + (uint64_t)k * TEAM;
+      if (v > total_v - 1) v = total_v - 1;
+      uint32_t c = 0;  // last segment with v0 <= v
 #pragma unroll
-    for (int k = 0; k < U; k++)
-      if (da[k]) *(GLOBAL v4u *)(da[k]) = r[k];
+      for (uint32_t st = 16; st; st >>= 1) {
+        const uint32_t i = c + st < nseg ? c + st : nseg - 1;
+        c = (c + st < nseg && sg[i].v0 <= v) ? c + st : c;
+      }
+      const Seg &g = sg[c];
+      const uint64_t w = 16 * (v - g.v0);
+      sa[k] = g.s + (g.a0 - g.d) + w;
+      da[k] = g.a0 + w;
+    }
+    v4u r[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) r[k] = *(const GLOBAL v4u_any *)(sa[k]);
+#pragma unroll
+    for (int k = 0; k < U; k++) *(GLOBAL v4u *)(da[k]) = r[k];
   }
 }
 
@@ -300,12 +324,10 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, 
       sg[2 * lane + 1] = make_seg(r.payload, st.src_base + off + first, sz - first);
     }
     wave_sync();
-    uint64_t nv = lane < 2 * j ? sg[lane].nv : 0;
-    const uint64_t nv_incl = wave_scan(nv, lane);
-    if (lane < 2 * j) sg[lane].v0 = nv_incl - nv;
-    const uint64_t total_v = shfl64(nv_incl, 63);
-    wave_sync();
-    seg_copy<64, 2>(sg, 2 * j, total_v, lane);
+    // one segment after another, each in full rounds of 4 KiB (a batch as
+    // one index space of vectors needs a search per vector, which kept the
+    // loads of a round from overlapping)
+    for (uint32_t g = 0; g < 2 * j; g++) team_copy<64, 4>(sg[g].d, sg[g].s, sg[g].n, lane);
     if (locking) {
       // publish in reservation order, carrying the predecessors' writes
       while (ld_rlx(tm_a) != my_tm) {
@@ -456,7 +478,7 @@ __device__ void run_consumer(const PumpArgs &a, uint32_t cid, uint32_t tid) {
         const uint64_t pos = (s_hb[ri] + s_rbytes[ri]) % P;
         const uint64_t first = P - pos < sz ? P - pos : sz;
         const uint64_t dst = s_pout[p] + s_outpos[p];
-        s_seg[nseg++] = make_seg(dst, s_rpay[ri] + pos, first);
+        if (first) s_seg[nseg++] = make_seg(dst, s_rpay[ri] + pos, first);
         if (sz > first) s_seg[nseg++] = make_seg(dst + first, s_rpay[ri], sz - first);
         s_rbytes[ri] += sz;
         s_outpos[p] += sz;
@@ -602,9 +624,11 @@ __device__ void run_lock_team(const PumpArgs &a, uint32_t uid, uint32_t tid) {
       for (uint32_t i = 0; i < n; i++) {
         const uint64_t sz = s_sz[i], pos = s_pos[i] % r.P;
         const uint64_t first = r.P - pos < sz ? r.P - pos : sz;
-        s_seg[nseg] = make_seg(s_out[i], r.payload + pos, first);
-        s_seg[nseg].v0 = v;
-        v += s_seg[nseg++].nv;
+        if (first) {
+          s_seg[nseg] = make_seg(s_out[i], r.payload + pos, first);
+          s_seg[nseg].v0 = v;
+          v += s_seg[nseg++].nv;
+        }
         if (sz > first) {
           s_seg[nseg] = make_seg(s_out[i] + first, r.payload, sz - first);
           s_seg[nseg].v0 = v;
