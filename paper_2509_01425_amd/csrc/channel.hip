@@ -169,18 +169,19 @@ __device__ __forceinline__ Seg make_seg(uint64_t d, uint64_t s, uint64_t n) {
 }
 
 // All TEAM threads copy nseg segments (held in LDS, every one non-empty, at
-// most 32) as one index space of 16-byte vectors, so a batch of small
+// most kMaxSegs) as one index space of 16-byte vectors, so a batch of small
 // messages costs about one memory round trip instead of one per message.
 // Branch-free like team_copy: the head and tail bytes (slot 32 g + j: j < 16
 // head byte j of segment g, else tail byte j - 16) and the vectors are
 // clamped into range, so repeated copies write equal values, and a vector's
-// segment is found by a fixed five-step binary search over the segments'
+// segment is found by a fixed binary search (log2 kMaxSegs steps) over the segments'
 // first vectors (v0) instead of a data-dependent loop; the compiler then
 // issues a round's U loads back to back.
+constexpr uint32_t kMaxSegs = 64;  // a power of two
 template <int TEAM, int U>
 __device__ void seg_copy(const Seg *sg, uint32_t nseg, uint64_t total_v, uint32_t t) {
   if (nseg == 0) return;
-  constexpr int kB = (32 * 32 + TEAM - 1) / TEAM;  // byte slots per thread
+  constexpr int kB = (32 * kMaxSegs + TEAM - 1) / TEAM;  // byte slots per thread
   unsigned char bv[kB];
   uint64_t bd[kB];
 #pragma unroll
@@ -208,7 +209,7 @@ __device__ void seg_copy(const Seg *sg, uint32_t nseg, uint64_t total_v, uint32_
       if (v > total_v - 1) v = total_v - 1;
       uint32_t c = 0;  // last segment with v0 <= v
 #pragma unroll
-      for (uint32_t st = 16; st; st >>= 1) {
+      for (uint32_t st = kMaxSegs / 2; st; st >>= 1) {
         const uint32_t i = c + st < nseg ? c + st : nseg - 1;
         c = (c + st < nseg && sg[i].v0 <= v) ? c + st : c;
       }
@@ -231,7 +232,8 @@ __device__ void seg_copy(const Seg *sg, uint32_t nseg, uint64_t total_v, uint32_
 // -5% on the locking one).
 constexpr uint32_t kProdBatch = 16;
 constexpr uint32_t kProdBatchLocking = 8;
-constexpr uint32_t kConsBatch = 16;  // messages a consumer takes at once
+constexpr uint32_t kConsBatch = 32;  // messages a consumer takes at once
+static_assert(2 * kConsBatch <= kMaxSegs, "a consumer batch is at most 2 segments per message");
 
 // One producer wave drives one stream: it takes as many of its next messages
 // as the ring has room for (up to kProdBatch, or kProdBatchLocking), copies

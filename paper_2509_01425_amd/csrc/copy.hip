@@ -18,9 +18,9 @@
 //   3. a piece is copied by its wave with 16-byte destination-aligned vector
 //      stores and 16-byte loads at whatever alignment the source has (the HSA
 //      ABI runs gfx950 in unaligned-access mode), `unroll` vectors in flight
-//      per lane; the at most 15 bytes before the first and after the last
-//      aligned destination vector are copied byte by byte, so no store ever
-//      touches a byte outside the request;
+//      per lane, branch-free (see copy_span); the at most 15 bytes before
+//      the first and after the last aligned destination vector are copied
+//      byte by byte, so no store ever touches a byte outside the request;
 //   4. completion counting is a separate small kernel (count.hip) queued
 //      behind the copy launches of a submission on the same stream: the
 //      kernel boundary makes every copied byte visible before any counter
@@ -44,10 +44,6 @@ __device__ __forceinline__ v4u load16(uint64_t a) { return *(const GLOBAL v4u_an
 // kernel, and streaming it past the caches measured ~2% faster on gfx950.
 __device__ __forceinline__ void store16(uint64_t a, v4u v) {
   __builtin_nontemporal_store(v, (GLOBAL v4u *)a);
-}
-
-__device__ __forceinline__ void copy_byte(uint64_t d, uint64_t s) {
-  *(GLOBAL unsigned char *)d = *(const GLOBAL unsigned char *)s;
 }
 
 // First index i in [0, n) with ends[i] > q (ends strictly increasing, q <
@@ -74,55 +70,56 @@ __device__ __forceinline__ uint32_t find_piece_owner(Ends ends, uint32_t n, uint
   return lo + (uint32_t)__ffsll((unsigned long long)m) - 1;
 }
 
-// Copy nv 16-byte vectors with one wavefront: destination d is 16-byte
-// aligned, source s is not necessarily.  Lane t moves vectors t, t + 64, ...
-// with U loads issued before the matching stores.
-template <int U>
-__device__ __forceinline__ void copy_body(uint64_t d, uint64_t s, uint64_t nv, uint32_t lane) {
-  constexpr uint64_t step = 64ull * U;
-  const uint64_t full = nv - nv % step;
-  uint64_t base = 0;
-  for (; base < full; base += step) {
-    v4u r[U];
-#pragma unroll
-    for (int k = 0; k < U; k++) r[k] = load16(s + (base + lane + 64ull * k) * 16);
-#pragma unroll
-    for (int k = 0; k < U; k++) store16(d + (base + lane + 64ull * k) * 16, r[k]);
-  }
-  v4u r[U];
-#pragma unroll
-  for (int k = 0; k < U; k++) {
-    uint64_t idx = base + lane + 64ull * k;
-    if (idx < nv) r[k] = load16(s + idx * 16);
-  }
-#pragma unroll
-  for (int k = 0; k < U; k++) {
-    uint64_t idx = base + lane + 64ull * k;
-    if (idx < nv) store16(d + idx * 16, r[k]);
-  }
-}
-
 // Copy destination bytes [lo, hi) from source address s (the source byte of
-// lo) with one wavefront.  The head [lo, a0) and tail [a1, hi) are each
-// shorter than 16 bytes: lanes 0..14 take the head, lanes 32..46 the tail.
-__device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s, uint32_t unroll,
-                                           uint32_t lane) {
+// lo) with one wavefront: 16-byte destination-aligned vectors, `unroll`
+// (U) per lane in flight, and the at most 15 head bytes [lo, a0) and 15 tail
+// bytes [a1, hi) one by one.  The code has no per-lane branch: past the last
+// vector a lane copies the last vector again, and every lane copies one byte
+// (lanes 0-15 the head bytes, 16-31 the tail bytes, repeating the last one
+// of a range, or byte lo when a range is empty; the other lanes byte lo), so
+// repeated stores write equal values inside the piece.  A bounds test per
+// access made the compiler wait for each access of a partial round in turn
+// (four memory latencies for the last round of a piece instead of one); the
+// byte is loaded before the vectors and stored after them, so its latency
+// overlaps theirs.
+template <int U>
+__device__ __forceinline__ void copy_span(uint64_t lo, uint64_t hi, uint64_t s, uint32_t lane) {
   uint64_t a0 = (lo + 15) & ~(uint64_t)15;
   if (a0 > hi) a0 = hi;
   uint64_t a1 = hi & ~(uint64_t)15;
   if (a1 < a0) a1 = a0;
-  if (lane < a0 - lo) copy_byte(lo + lane, s + lane);
-  if (lane >= 32 && lane - 32 < hi - a1) {
-    uint64_t o = (a1 - lo) + (lane - 32);
-    copy_byte(lo + o, s + o);
-  }
+  const uint64_t nh = a0 - lo, nt = hi - a1;
+  uint64_t bo = 0;  // this lane's byte, as an offset from lo
+  if (lane < 16)
+    bo = nh ? (lane < nh ? lane : nh - 1) : 0;
+  else if (lane < 32)
+    bo = nt ? (a1 - lo) + (lane - 16 < nt ? lane - 16 : nt - 1) : 0;
+  const unsigned char byte = *(const GLOBAL unsigned char *)(s + bo);
   const uint64_t nv = (a1 - a0) >> 4;
-  if (nv == 0) return;
-  const uint64_t d16 = a0, s16 = s + (a0 - lo);
+  const uint64_t s16 = s + nh;
+  constexpr uint64_t step = 64ull * U;
+  for (uint64_t base = 0; base < nv; base += step) {
+    uint64_t o[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      const uint64_t i = base + lane + 64ull * k;
+      o[k] = 16 * (i < nv ? i : nv - 1);
+    }
+    v4u r[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) r[k] = load16(s16 + o[k]);
+#pragma unroll
+    for (int k = 0; k < U; k++) store16(a0 + o[k], r[k]);
+  }
+  *(GLOBAL unsigned char *)(lo + bo) = byte;
+}
+
+__device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s, uint32_t unroll,
+                                           uint32_t lane) {
   if (unroll >= 4)
-    copy_body<4>(d16, s16, nv, lane);
+    copy_span<4>(lo, hi, s, lane);
   else
-    copy_body<2>(d16, s16, nv, lane);
+    copy_span<2>(lo, hi, s, lane);
 }
 
 // Piece j (of length L) of the request dst <- src, size bytes: pieces start
