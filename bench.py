@@ -142,8 +142,11 @@ def channel_rig(torch, H, ctx, plan, mpsc_mode, seed, stream=0):
 def bench_channels(torch, H, mpsc_mode, steps=3, warmup=1, seed=5):
     """The channel configuration (1,024 SPSC + 64 MPSC x 8 producers, 1e6
     messages, 1 MiB / 64-entry rings) through one persistent pump per step.
-    GB/s counts 4 bytes per payload byte (source read, ring write, ring read,
-    output write) plus the 8-byte entry written and read per message."""
+    The message tables (source offset and size of every message) are inputs
+    resident in device memory (HICR_PUMP_DEVICE_TABLES), uploaded once like
+    the sources.  GB/s counts 4 bytes per payload byte (source read, ring
+    write, ring read, output write) plus the 8-byte entry written and read per
+    message."""
     from workloads import channels as wc
     plan = wc.plan()
     stream = torch.cuda.Stream()
@@ -151,13 +154,15 @@ def bench_channels(torch, H, mpsc_mode, steps=3, warmup=1, seed=5):
     assert rc == H.OK
     rig = channel_rig(torch, H, ctx, plan, mpsc_mode, seed, stream.cuda_stream)
     ts = torch.zeros(2 * plan.n_msgs, dtype=torch.int64, device="cuda")
+    offs = torch.from_numpy(plan.msg_src_off.astype(np.int64)).cuda()
+    sizes = torch.from_numpy(plan.msg_size.astype(np.int64)).cuda()
     torch.cuda.synchronize()
     times = []
     for k in range(warmup + steps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        rc = H.hicr_channel_pump(ctx, rig["streams"], plan.msg_src_off, plan.msg_size, 0,
-                                 ts.data_ptr(), timeout_ns=10 * 10**9)
+        rc = H.hicr_channel_pump(ctx, rig["streams"], offs.data_ptr(), sizes.data_ptr(), 0,
+                                 ts.data_ptr(), timeout_ns=10 * 10**9, n_msgs=plan.n_msgs)
         e1.record(stream)
         assert rc == H.OK, H.hicr_last_error(ctx)
         assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)

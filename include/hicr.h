@@ -367,8 +367,9 @@ typedef struct {
 } hicr_stream;
 
 typedef struct {
-  const uint64_t *msg_src_off; /* host array [n_msgs]                              */
-  const uint64_t *msg_size;    /* host array [n_msgs]; FIXED channels: token_bytes */
+  const uint64_t *msg_src_off; /* array [n_msgs]: host memory, or device memory with
+                                  HICR_PUMP_DEVICE_TABLES                          */
+  const uint64_t *msg_size;    /* array [n_msgs]; FIXED channels: token_bytes      */
   uint64_t n_msgs;
   uint32_t *trace_dev;   /* optional device array: for every consumed message, its
                             stream index; channels in order of first appearance in
@@ -381,7 +382,19 @@ typedef struct {
                             consume time of every message (100 MHz device clock)    */
   uint64_t timeout_ns;   /* a wait that sees no progress for this long ends the
                             pump with HICR_ETIMEDOUT at the next fence (0: 10 s)    */
+  uint32_t flags;        /* HICR_PUMP_* bits                                       */
+  uint32_t reserved;     /* 0                                                      */
 } hicr_pump_io;
+
+/* msg_src_off and msg_size are device arrays the caller keeps valid (and
+ * unchanged) until the pump has finished: nothing is copied from the host.
+ * Variable-size channels only.  The host then cannot check the messages;
+ * every producer checks each of its messages before moving a byte (size at
+ * most the ring's payload, the source range inside its source slot, the
+ * stream's output inside its output slot) and a bad one ends the pump with
+ * HICR_EDEVICE at the next fence.  Rings are balanced over consumer
+ * workgroups by message count instead of bytes. */
+#define HICR_PUMP_DEVICE_TABLES 0x1u
 
 /* Run every stream through its device-endpoint channel in one persistent
  * launch on `stream`: one GPU wave per producer stream.  The consumer side

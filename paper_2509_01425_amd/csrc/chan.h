@@ -82,8 +82,10 @@ struct DevStream {
   uint64_t out_base;   // device address of the output slot
   uint64_t first_msg;  // index into msg_off/msg_size
   uint64_t n_msgs;
-  uint64_t out_bytes;  // sum of the stream's message sizes (bound of its output)
+  uint64_t out_bytes;  // bound of its output: the sum of the stream's message sizes,
+                       // or the output slot's size when the tables are on the device
   uint64_t trace_base; // first trace slot of the stream (rings consumed on their own)
+  uint64_t src_bytes;  // size of the source slot
 };
 
 // Per-workgroup role: kind 0 = up to four producer waves (ids = streams),

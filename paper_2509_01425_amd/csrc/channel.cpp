@@ -335,7 +335,7 @@ namespace hicr {
 // is described by *x (event, buffers to free, abort word, channels).
 int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *msg_off,
                 const uint64_t *msg_size, uint64_t n_msgs, uint32_t *trace_dev, uint64_t *ts_dev,
-                uint64_t timeout_ns, hipStream_t s, Extra *xout) {
+                uint64_t timeout_ns, hipStream_t s, Extra *xout, bool dev_tables) {
   const uint32_t n = (uint32_t)st.size();
   if (n_msgs && (!msg_off || !msg_size)) return fail(c, HICR_EINVAL, "message arrays missing");
   // channels in order of first appearance
@@ -359,6 +359,12 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
     }
     if (st[i].first_msg > n_msgs || st[i].n_msgs > n_msgs - st[i].first_msg)
       return fail(c, HICR_ERANGE, "stream %u: messages outside the arrays", i);
+    if (dev_tables) {
+      // the producers check every message on the device
+      if (ch->cfg.kind != HICR_CH_VAR)
+        return fail(c, HICR_EINVAL, "stream %u: device message tables need a variable-size channel", i);
+      continue;
+    }
     uint64_t total = 0;
     for (uint64_t j = st[i].first_msg; j < st[i].first_msg + st[i].n_msgs; j++) {
       const uint64_t sz = msg_size[j], o = msg_off[j];
@@ -383,10 +389,16 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   // so one channel's producers do not all wait on one workgroup.
   const uint32_t prod_wgs = (n + 3) / 4;
   const uint64_t cap = (uint64_t)c->n_cu * (uint64_t)c->pump_occ;
+  // bytes per stream; with device tables the host balances by message count
   std::vector<uint64_t> stream_bytes(n, 0);
-  for (uint32_t i = 0; i < n; i++)
+  for (uint32_t i = 0; i < n; i++) {
+    if (dev_tables) {
+      stream_bytes[i] = st[i].n_msgs;
+      continue;
+    }
     for (uint64_t j = st[i].first_msg; j < st[i].first_msg + st[i].n_msgs; j++)
       stream_bytes[i] += msg_size[j];
+  }
   std::vector<uint64_t> chan_trace(chans.size());
   std::vector<uint64_t> stream_trace(n, 0);
   uint64_t trace_total = 0;
@@ -535,8 +547,9 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
     ds[i].out_base = st[i].out_base;
     ds[i].first_msg = st[i].first_msg;
     ds[i].n_msgs = st[i].n_msgs;
-    ds[i].out_bytes = stream_bytes[i];
+    ds[i].out_bytes = dev_tables ? st[i].out_size : stream_bytes[i];
     ds[i].trace_base = stream_trace[i];
+    ds[i].src_bytes = st[i].src_size;
   }
   if (trace_dev) {
     int rc = check_dev_range(c, trace_dev, trace_total * 4, "trace_dev");
@@ -560,7 +573,8 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
            o_st = align(o_ch + dch.size() * sizeof(DevChannel)),
            o_sop = align(o_st + ds.size() * sizeof(DevStream)),
            o_role = align(o_sop + sop.size() * 4), o_off = align(o_role + roles.size() * sizeof(DevRole)),
-           o_size = align(o_off + n_msgs * 8), upload = align(o_size + n_msgs * 8),
+           n_up = dev_tables ? 0 : n_msgs,  // message tables uploaded from the host
+           o_size = align(o_off + n_up * 8), upload = align(o_size + n_up * 8),
            o_team = upload, total = align(o_team + team_bytes);
   Extra x;
   x.pump = true;
@@ -591,9 +605,9 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   std::memcpy(h + o_st, ds.data(), ds.size() * sizeof(DevStream));
   std::memcpy(h + o_sop, sop.data(), sop.size() * 4);
   std::memcpy(h + o_role, roles.data(), roles.size() * sizeof(DevRole));
-  if (n_msgs) {
-    std::memcpy(h + o_off, msg_off, n_msgs * 8);
-    std::memcpy(h + o_size, msg_size, n_msgs * 8);
+  if (n_up) {
+    std::memcpy(h + o_off, msg_off, n_up * 8);
+    std::memcpy(h + o_size, msg_size, n_up * 8);
   }
   char *d = static_cast<char *>(x.d_buf);
   PumpArgs a;
@@ -602,8 +616,8 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   a.streams = reinterpret_cast<const DevStream *>(d + o_st);
   a.stream_of_prod = reinterpret_cast<const uint32_t *>(d + o_sop);
   a.roles = reinterpret_cast<const DevRole *>(d + o_role);
-  a.msg_off = reinterpret_cast<const uint64_t *>(d + o_off);
-  a.msg_size = reinterpret_cast<const uint64_t *>(d + o_size);
+  a.msg_off = dev_tables ? msg_off : reinterpret_cast<const uint64_t *>(d + o_off);
+  a.msg_size = dev_tables ? msg_size : reinterpret_cast<const uint64_t *>(d + o_size);
   a.trace = trace_dev;
   a.ts_push = ts_dev;
   a.ts_pop = ts_dev ? ts_dev + n_msgs : nullptr;
@@ -672,7 +686,8 @@ extern "C" {
 
 int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_pump_io *io,
                       void *stream) {
-  if (!c || !io || (n && !st)) return HICR_EINVAL;
+  if (!c || !io || (n && !st) || (io->flags & ~HICR_PUMP_DEVICE_TABLES) || io->reserved)
+    return HICR_EINVAL;
   std::lock_guard<std::mutex> g(c->mu);
   (void)hipSetDevice(c->device);
   std::vector<PumpStream> ps(n);
@@ -693,7 +708,8 @@ int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_
   Extra x;
   int rc = pump_launch(c, ps, io->msg_src_off, io->msg_size, io->n_msgs, io->trace_dev,
                        io->ts_dev, io->timeout_ns,
-                       stream ? static_cast<hipStream_t>(stream) : c->stream, &x);
+                       stream ? static_cast<hipStream_t>(stream) : c->stream, &x,
+                       (io->flags & HICR_PUMP_DEVICE_TABLES) != 0);
   if (rc == HICR_OK && x.ev) c->extra.push_back(x);
   return rc;
 }

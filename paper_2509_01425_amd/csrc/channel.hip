@@ -262,6 +262,17 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, 
     const uint64_t sz = have ? a.msg_size[st.first_msg + m + lane] : 0;
     const uint64_t off = have ? a.msg_off[st.first_msg + m + lane] : 0;
     const uint64_t incl = wave_scan(sz, lane);
+    // every message is checked before a byte of it moves (the host has not
+    // seen message tables that live on the device): it fits the ring, its
+    // source range lies in the stream's source slot, its output in the
+    // output slot
+    const bool bad = have && (sz > r.P || off > st.src_bytes || sz > st.src_bytes - off ||
+                              out_run + incl > st.out_bytes);
+    if (__ballot(bad)) {
+      if (lane == 0)
+        __hip_atomic_fetch_or(&a.err[0], kErrCorrupt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
     uint64_t ticket = 0;
     if (locking) {
       if (lane == 0)

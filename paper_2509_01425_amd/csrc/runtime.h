@@ -158,9 +158,11 @@ struct PumpStream {
   uint64_t src_base, src_size, out_base, out_size;
   uint64_t first_msg, n_msgs;
 };
+// msg_off/msg_size: host arrays, or (dev_tables) device arrays the kernel
+// reads in place and checks itself.
 int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *msg_off,
                 const uint64_t *msg_size, uint64_t n_msgs, uint32_t *trace_dev, uint64_t *ts_dev,
-                uint64_t timeout_ns, hipStream_t s, Extra *xout);
+                uint64_t timeout_ns, hipStream_t s, Extra *xout, bool dev_tables = false);
 int pump_finish(hicr_ctx c, Extra &x);
 uint64_t channel_payload_limit(struct ::hicr_channel_s *ch);
 int wait_extra(hicr_ctx c);

@@ -71,7 +71,11 @@ class hicr_stream(ctypes.Structure):
 class hicr_pump_io(ctypes.Structure):
     _fields_ = [("msg_src_off", ctypes.c_void_p), ("msg_size", ctypes.c_void_p),
                 ("n_msgs", ctypes.c_uint64), ("trace_dev", ctypes.c_void_p),
-                ("ts_dev", ctypes.c_void_p), ("timeout_ns", ctypes.c_uint64)]
+                ("ts_dev", ctypes.c_void_p), ("timeout_ns", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+PUMP_DEVICE_TABLES = 0x1
 
 
 REQ_COPY, REQ_BURST = 0, 1
@@ -362,16 +366,23 @@ def hicr_channel_depth(ch, ring: int):
     return rc, m.value, b.value
 
 
-def hicr_channel_pump(ctx, streams, msg_src_off: np.ndarray, msg_size: np.ndarray,
-                      trace_dev: int = 0, ts_dev: int = 0, timeout_ns: int = 0, stream: int = 0):
-    """streams: sequence of (channel, producer, src_slot, out_slot, first_msg, n_msgs)."""
+def hicr_channel_pump(ctx, streams, msg_src_off, msg_size, trace_dev: int = 0, ts_dev: int = 0,
+                      timeout_ns: int = 0, stream: int = 0, n_msgs: int = None):
+    """streams: sequence of (channel, producer, src_slot, out_slot, first_msg, n_msgs).
+    msg_src_off / msg_size: host arrays, or device addresses (ints, with
+    n_msgs given) for HICR_PUMP_DEVICE_TABLES."""
     arr = (hicr_stream * max(len(streams), 1))()
     for i, (ch, p, src, out, first, n) in enumerate(streams):
         arr[i] = hicr_stream(ch, p, src, out, 0, first, n)
-    off = np.ascontiguousarray(msg_src_off, dtype=np.uint64)
-    size = np.ascontiguousarray(msg_size, dtype=np.uint64)
-    io = hicr_pump_io(off.ctypes.data if off.size else None, size.ctypes.data if size.size else None,
-                      off.size, trace_dev or None, ts_dev or None, timeout_ns)
+    if isinstance(msg_src_off, int):
+        io = hicr_pump_io(msg_src_off or None, msg_size or None, n_msgs, trace_dev or None,
+                          ts_dev or None, timeout_ns, PUMP_DEVICE_TABLES, 0)
+    else:
+        off = np.ascontiguousarray(msg_src_off, dtype=np.uint64)
+        size = np.ascontiguousarray(msg_size, dtype=np.uint64)
+        io = hicr_pump_io(off.ctypes.data if off.size else None,
+                          size.ctypes.data if size.size else None, off.size, trace_dev or None,
+                          ts_dev or None, timeout_ns, 0, 0)
     return lib().hicr_channel_pump(ctx, arr, len(streams), ctypes.byref(io), stream or None)
 
 

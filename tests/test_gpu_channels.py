@@ -319,6 +319,68 @@ def test_pump_small_mixed_plan(env, mode):
 
 
 @pytest.mark.parametrize("mode", ["lock", "nolock"])
+def test_pump_device_tables(env, mode):
+    """The small mixed plan with its message tables in device memory
+    (HICR_PUMP_DEVICE_TABLES): the same bytes as the oracle, every message
+    checked by its producer instead of the host."""
+    torch, H, wd, ctx = env
+    from bench import channel_rig
+    seed = 405
+    _say("pump device tables", mode)
+    plan = wc.plan(n_spsc=6, n_mpsc=3, K=3, total_msgs=1500, lo=1, hi=8192, P=8192, E=8,
+                   src_bytes=1 << 16, batch=7)
+    plan.msg_size[::37] = 0  # zero-byte messages take an entry and no bytes
+    hmode = H.CH_MPSC_LOCK if mode == "lock" else H.CH_MPSC_NOLOCK
+    rig = channel_rig(torch, H, ctx, plan, hmode, seed)
+    trace = torch.zeros(plan.n_msgs, dtype=torch.int32, device="cuda")
+    offs = torch.from_numpy(plan.msg_src_off.astype(np.int64)).cuda()
+    sizes = torch.from_numpy(plan.msg_size.astype(np.int64)).cuda()
+    torch.cuda.synchronize()
+    rc = H.hicr_channel_pump(ctx, rig["streams"], offs.data_ptr(), sizes.data_ptr(),
+                             trace.data_ptr(), timeout_ns=5 * 10**9, n_msgs=plan.n_msgs)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+    _check_plan(torch, H, rig, plan, seed, mode, trace)
+    for ch in rig["channels"]:
+        assert H.hicr_channel_destroy(ch) == H.OK
+
+
+@pytest.mark.parametrize("bad", ["size", "offset"])
+def test_pump_device_tables_bad_message_is_reported(env, bad):
+    """A message in device tables that does not fit its ring (or lies outside
+    its source slot) is caught by its producer before a byte moves: the pump
+    ends, the fence reports HICR_EDEVICE and the channel is broken.  Fixed-size
+    channels and unknown flags are refused on the host."""
+    torch, H, wd, ctx = env
+    from bench import channel_rig
+    _say("pump device tables bad", bad)
+    plan = wc.plan(n_spsc=4, n_mpsc=0, K=1, total_msgs=200, lo=1, hi=4096, P=8192, E=8,
+                   src_bytes=1 << 16, batch=7)
+    rig = channel_rig(torch, H, ctx, plan, H.CH_MPSC_NOLOCK, 11)
+    o = plan.msg_src_off.astype(np.int64).copy()
+    z = plan.msg_size.astype(np.int64).copy()
+    k = int(plan.msg_begin[2]) + 5  # a message of stream 2
+    if bad == "size":
+        z[k] = plan.P + 1
+    else:
+        o[k] = plan.src_bytes - int(z[k]) + 1
+    offs, sizes = torch.from_numpy(o).cuda(), torch.from_numpy(z).cuda()
+    torch.cuda.synchronize()
+    rc = H.hicr_channel_pump(ctx, rig["streams"], offs.data_ptr(), sizes.data_ptr(),
+                             timeout_ns=2 * 10**9, n_msgs=plan.n_msgs)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.EDEVICE
+    # the channel the bad message went through is broken
+    assert H.hicr_channel_pump(ctx, rig["streams"], plan.msg_src_off, plan.msg_size) == H.EINVAL
+    for ch in rig["channels"]:
+        assert H.hicr_channel_destroy(ch) == H.OK
+    # unknown flag bits are refused before anything runs
+    io = H.hicr_pump_io(None, None, 0, None, None, 0, 0x2, 0)
+    arr = (H.hicr_stream * 1)()
+    assert H.lib().hicr_channel_pump(ctx, arr, 0, H.ctypes.byref(io), None) == H.EINVAL
+
+
+@pytest.mark.parametrize("mode", ["lock", "nolock"])
 def test_pump_full_size_sampled(env, mode):
     """The measured channel configuration: 1,024 SPSC + 64 MPSC x 8 producers,
     1e6 messages of 16 B..256 KiB through 1 MiB / 64-entry rings, in one
