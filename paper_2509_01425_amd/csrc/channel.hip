@@ -19,10 +19,12 @@
 // poll with relaxed device-scope loads and take one acquire fence once the
 // condition holds (an acquire per poll would invalidate the L2 on every
 // spin).  Producers publish up to 16 messages per release (8 on a locking
-// ring); consumers take up to 16 per release across all of their rings, and
-// copy each batch as one index space of 16-byte vectors.  The host launches no more workgroups
-// than the device holds at once, and every wait gives up after a
-// no-progress time-out or on the abort word, so every wave exits.
+// ring) and copy a batch message by message; consumers take up to 32 per
+// release across all of their rings and copy each batch as one index space
+// of 16-byte vectors.  Producers check every message against their stream's
+// slots before moving a byte.  The host launches no more workgroups than the
+// device holds at once, and every wait gives up after a no-progress time-out
+// or on the abort word, so every wave exits.
 #include "chan.h"
 
 namespace hicr {
