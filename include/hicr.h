@@ -160,7 +160,11 @@ int hicr_memcpy(hicr_ctx ctx, hicr_slot dst, uint64_t dst_off, hicr_slot src, ui
  * checked first; on the first invalid request nothing is enqueued, the code
  * of that request is returned and its index stored in *bad_index_or_null.
  * `descs` is copied before the call returns.  s_or_null NULL selects the
- * context default. */
+ * context default.  A batch of 8,192 requests or more is uploaded on a
+ * private stream that `stream` waits for (so the upload overlaps earlier
+ * copies); 16,384 or more are checked by several host threads.  A
+ * submission stages through host memory and is not meant for HIP graph
+ * capture: persistent plans (below) are. */
 int hicr_memcpy_batch(hicr_ctx ctx, const hicr_desc *descs, uint64_t n,
                       const hicr_sched *s_or_null, void *stream, uint64_t *bad_index_or_null);
 /* Sec. 3.1.4 fence: return once every transfer submitted on this context

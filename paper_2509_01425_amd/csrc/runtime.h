@@ -31,9 +31,12 @@ struct Sub {
   void *h = nullptr;
   void *d = nullptr;
   uint64_t cap = 0;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr;     // end of the submission's last launch
+  hipEvent_t up_ev = nullptr;  // end of its upload, when that ran on the upload stream
   bool inflight = false;
 };
+
+class HostPool;  // host threads that validate and pack large batches (runtime.cpp)
 
 // One copy launch of a batch: requests [i0, i1) with `bytes` bytes and
 // `pieces` pieces (exact on the LDS path, at least that many on the table
@@ -75,6 +78,8 @@ struct hicr_ctx_s {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipStream_t aux = nullptr;  // counter reads, never waits on `stream`
+  hipStream_t up = nullptr;   // uploads of large batches, overlapping earlier copies
+  hicr::HostPool *pool = nullptr;  // created at the first large submission
   int n_cu = 1;
   int occ = 1;       // copy workgroups per CU that fit
   int grid_per_cu = 0;  // copy workgroups per CU launched (0: per-schedule default)
