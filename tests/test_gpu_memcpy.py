@@ -235,6 +235,66 @@ def test_large_batch_scanned_table_all_classes(env):
     assert H.hicr_slot_deregister(ctx, b) == H.OK
 
 
+def test_large_batch_threaded_checks_and_upload_stream(env):
+    """24,000 requests: checked by several host threads and uploaded on the
+    private stream.  Two bad requests (in different threads' parts): the
+    lower index is reported and nothing moves.  Then the valid batch and a
+    small batch right behind it on the same stream, the small one reading
+    what the large one wrote, both against the oracle."""
+    torch, H, wd, ctx = env
+    n = 24_000
+    g = np.random.default_rng(17)
+    sz = g.integers(1, 600, n)
+    dst = np.concatenate([[0], np.cumsum(sz + 3)[:-1]]) + 1
+    src_base = int(dst[-1] + sz[-1] + 64)
+    src = np.concatenate([[0], np.cumsum(sz + 5)[:-1]]) + 7
+    tail_base = src_base + int(src[-1] + sz[-1] + 64)
+    pool_len = tail_base + 4096
+    seed = 31
+    _say("threaded checks", n, pool_len)
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), pool_len, seed)
+    torch.cuda.synchronize()
+    rc, a = H.hicr_slot_register(ctx, pool.data_ptr(), src_base, H.MEM_HBM)
+    rc2, b = H.hicr_slot_register(ctx, pool.data_ptr() + src_base, pool_len - src_base, H.MEM_HBM)
+    assert rc == rc2 == H.OK
+    d = np.zeros(n, dtype=H.DESC_DTYPE)
+    d["dst_slot"], d["src_slot"] = a, b
+    d["dst_off"], d["src_off"], d["size"] = dst, src, sz
+    bad = d.copy()
+    bad[20_000]["size"] = src_base  # past the end of slot a
+    bad[13_000]["src_slot"] = 999_999
+    assert H.hicr_memcpy_batch(ctx, bad) == (H.EBADSLOT, 13_000)
+    bad[13_000]["src_slot"] = b
+    assert H.hicr_memcpy_batch(ctx, bad) == (H.ERANGE, 20_000)
+    assert H.hicr_fence(ctx) == H.OK
+    assert H.hicr_slot_counters(ctx, a) == (H.OK, 0, 0)
+    host = content(seed, 0, pool_len)
+    assert np.array_equal(pool.cpu().numpy(), host)
+    # the valid batch, then a small batch that copies part of its output
+    small = np.zeros(4, dtype=H.DESC_DTYPE)
+    small["dst_slot"], small["src_slot"] = b, a
+    small["dst_off"] = tail_base - src_base + np.arange(4) * 1000
+    small["src_off"] = dst[[0, 5000, 12_000, 23_000]]
+    small["size"] = 900
+    assert H.hicr_memcpy_batch(ctx, d, H.hicr_sched_class(5)[1])[0] == H.OK
+    assert H.hicr_memcpy_batch(ctx, small, H.hicr_sched_class(5)[1])[0] == H.OK
+    assert H.hicr_fence(ctx) == H.OK
+    oc = oracle.Ctx()
+    oa = oc.register(host, offset=0, size=src_base)[1]
+    ob = oc.register(host, offset=src_base, size=pool_len - src_base)[1]
+    for batch in (d, small):
+        od = batch.copy()
+        od["dst_slot"] = np.where(batch["dst_slot"] == a, oa, ob)
+        od["src_slot"] = np.where(batch["src_slot"] == a, oa, ob)
+        assert oc.memcpy_batch(od)[0] == oracle.OK
+    assert np.array_equal(pool.cpu().numpy(), host)
+    assert H.hicr_slot_counters(ctx, a) == (H.OK, 4, n)
+    assert H.hicr_slot_counters(ctx, b) == (H.OK, n, 4)
+    assert H.hicr_slot_deregister(ctx, a) == H.OK
+    assert H.hicr_slot_deregister(ctx, b) == H.OK
+
+
 def test_single_memcpy_broadcast_and_fence_slot(env):
     """One message copied to many destinations with single memcpy calls and
     one fence (the paper's broadcast example, on one memory space)."""
