@@ -261,16 +261,14 @@ void pack_batch(hicr_ctx c, const hicr_desc *d, uint64_t n, uint64_t *h) {
 class HostPool {
  public:
   explicit HostPool(int extra) {
-    for (int i = 0; i < extra; i++) th_.emplace_back([this, i] { loop(i + 1); });
-  }
-  ~HostPool() {
-    {
-      std::lock_guard<std::mutex> g(m_);
-      quit_ = true;
+    try {
+      for (int i = 0; i < extra; i++) th_.emplace_back([this, i] { loop(i + 1); });
+    } catch (...) {
+      stop();  // join the threads already started, then report the failure
+      throw;
     }
-    cv_.notify_all();
-    for (std::thread &t : th_) t.join();
   }
+  ~HostPool() { stop(); }
   int size() const { return (int)th_.size() + 1; }
   void run(const std::function<void(int)> &f) {
     {
@@ -287,6 +285,15 @@ class HostPool {
   }
 
  private:
+  void stop() {
+    {
+      std::lock_guard<std::mutex> g(m_);
+      quit_ = true;
+    }
+    cv_.notify_all();
+    for (std::thread &t : th_)
+      if (t.joinable()) t.join();
+  }
   void loop(int part) {
     uint64_t seen = 0;
     for (;;) {
@@ -358,10 +365,15 @@ int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
   uint64_t *h = static_cast<uint64_t *>(s.h);
   uint64_t first_bad = n;
   int bad_rc = HICR_OK;
-  if (n >= kPoolMin) {
-    if (!c->pool) {
+  if (n >= kPoolMin && !c->pool && !c->pool_failed) {
+    // no exception crosses the C ABI: a pool that cannot start its threads
+    // leaves the checks on the calling thread
+    try {
       const int hw = (int)std::thread::hardware_concurrency();
-      c->pool = new (std::nothrow) HostPool(std::max(0, std::min(3, hw - 1)));
+      c->pool = new HostPool(std::max(0, std::min(3, hw - 1)));
+    } catch (...) {
+      c->pool = nullptr;
+      c->pool_failed = true;
     }
   }
   if (n >= kPoolMin && c->pool && c->pool->size() > 1) {

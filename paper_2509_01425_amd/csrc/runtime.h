@@ -80,6 +80,7 @@ struct hicr_ctx_s {
   hipStream_t aux = nullptr;  // counter reads, never waits on `stream`
   hipStream_t up = nullptr;   // uploads of large batches, overlapping earlier copies
   hicr::HostPool *pool = nullptr;  // created at the first large submission
+  bool pool_failed = false;        // its threads could not be started
   int n_cu = 1;
   int occ = 1;       // copy workgroups per CU that fit
   int grid_per_cu = 0;  // copy workgroups per CU launched (0: per-schedule default)
