@@ -94,7 +94,11 @@ __device__ __forceinline__ void copy_span(uint64_t lo, uint64_t hi, uint64_t s, 
     bo = nh ? (lane < nh ? lane : nh - 1) : 0;
   else if (lane < 32)
     bo = nt ? (a1 - lo) + (lane - 16 < nt ? lane - 16 : nt - 1) : 0;
-  const unsigned char byte = *(const GLOBAL unsigned char *)(s + bo);
+  // (lo and hi are the same in every lane: a piece without head or tail
+  // bytes, such as an aligned row, skips the byte copy altogether)
+  const bool bytes = (nh | nt) != 0;
+  unsigned char byte = 0;
+  if (bytes) byte = *(const GLOBAL unsigned char *)(s + bo);
   const uint64_t nv = (a1 - a0) >> 4;
   const uint64_t s16 = s + nh;
   constexpr uint64_t step = 64ull * U;
@@ -111,7 +115,7 @@ __device__ __forceinline__ void copy_span(uint64_t lo, uint64_t hi, uint64_t s, 
 #pragma unroll
     for (int k = 0; k < U; k++) store16(a0 + o[k], r[k]);
   }
-  *(GLOBAL unsigned char *)(lo + bo) = byte;
+  if (bytes) *(GLOBAL unsigned char *)(lo + bo) = byte;
 }
 
 __device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s, uint32_t unroll,
