@@ -17,7 +17,7 @@ on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sched CLASS|tuned|learned]
        python bench.py --calibrate-copy   (plain-copy kernel for counter scaling)
-       python bench.py --workload {channels,learned,serving,pingpong,tiny,halo}
+       python bench.py --workload {channels,learned,serving,pingpong,tiny,halo,memspace}
 """
 import argparse
 import hashlib
@@ -409,6 +409,66 @@ def parse_sched(H, text):
     return s
 
 
+def bench_memspace(torch, H, size=1 << 30, reps=5):
+    """Memory spaces: slot copies between HBM and pinned host memory (the
+    host link) with the fused copy kernel -- one request of `size` bytes, and
+    the same bytes as 4,096 requests -- in both directions, beside the DMA
+    engine's copy of the same bytes (torch copy_) as the link's reference.
+    GB/s counts the bytes moved over the link once."""
+    stream = torch.cuda.Stream()
+    rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
+    assert rc == H.OK
+    dev = torch.empty(size, dtype=torch.uint8, device="cuda")
+    host = torch.empty(size, dtype=torch.uint8).pin_memory()
+    dev.fill_(7)
+    host.fill_(9)
+    torch.cuda.synchronize()
+    rc, sd = H.hicr_slot_register(ctx, dev.data_ptr(), size, H.MEM_HBM)
+    rc2, sh = H.hicr_slot_register(ctx, host.data_ptr(), size, H.MEM_HOST)
+    assert rc == rc2 == H.OK, H.hicr_last_error(ctx)
+    sched = H.hicr_sched_class(5)[1]
+
+    def batch(dst, src, n):
+        d = np.zeros(n, dtype=H.DESC_DTYPE)
+        per = size // n
+        d["dst_slot"], d["src_slot"] = dst, src
+        d["dst_off"] = np.arange(n, dtype=np.uint64) * np.uint64(per)
+        d["src_off"] = d["dst_off"]
+        d["size"] = per
+        return d
+
+    def timed(fn):
+        fn()
+        stream.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return round(size / (float(np.median(ts)) * 1e-3) / 1e9, 1)
+
+    def hicr_copy(d):
+        def fn():
+            assert H.hicr_memcpy_batch(ctx, d, sched)[0] == H.OK
+            assert H.hicr_fence(ctx) == H.OK
+        return fn
+
+    out = {"workload": f"{size >> 20} MiB between an HBM slot and a pinned host slot", "bytes": size}
+    for name, dst, src in (("host_to_hbm", sd, sh), ("hbm_to_host", sh, sd)):
+        out[name] = {"memcpy_1_request_gbps": timed(hicr_copy(batch(dst, src, 1))),
+                     "memcpy_4096_requests_gbps": timed(hicr_copy(batch(dst, src, 4096)))}
+    with torch.cuda.stream(stream):
+        out["host_to_hbm"]["dma_copy_gbps"] = timed(lambda: dev.copy_(host, non_blocking=True))
+        out["hbm_to_host"]["dma_copy_gbps"] = timed(lambda: host.copy_(dev, non_blocking=True))
+    H.hicr_ctx_destroy(ctx)
+    del dev, host
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_tiny(torch, H, reps=1000, warmup=50):
     """Submit-to-fence latency of the tiny batch (64 packed slots, 256
     requests of 1..8 KiB): one hicr_memcpy_batch + hicr_fence per rep, and
@@ -530,7 +590,7 @@ def main():
                     help="copy workgroups per CU (0: the library's per-class default)")
     ap.add_argument("--workload", default="batched",
                     choices=["batched", "channels", "learned", "serving", "pingpong", "tiny",
-                             "halo"])
+                             "halo", "memspace"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-budget", type=float, default=200e9)
     ap.add_argument("--learned-train", type=int, default=20000)
@@ -560,6 +620,9 @@ def main():
         return
     if args.workload == "tiny":
         print(json.dumps({"tiny": bench_tiny(torch, H)}), flush=True)
+        return
+    if args.workload == "memspace":
+        print(json.dumps({"memspace": bench_memspace(torch, H)}), flush=True)
         return
     if args.workload == "pingpong":
         print(json.dumps({"pingpong": bench_pingpong(torch, H)}), flush=True)
