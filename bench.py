@@ -463,6 +463,42 @@ def bench_memspace(torch, H, size=1 << 30, reps=5):
     with torch.cuda.stream(stream):
         out["host_to_hbm"]["dma_copy_gbps"] = timed(lambda: dev.copy_(host, non_blocking=True))
         out["hbm_to_host"]["dma_copy_gbps"] = timed(lambda: host.copy_(dev, non_blocking=True))
+    # data objects: a published object fetched by get + fence -- small ones
+    # for latency, a large one for bandwidth (HBM to HBM, then host to HBM)
+    half = size // 2
+    objs = {}
+    for name, slot, off, n in (("obj_4KiB_hbm", sd, 0, 4096), ("obj_half_hbm", sd, 0, half),
+                               ("obj_4KiB_host", sh, 0, 4096)):
+        rc, oid = H.hicr_dobj_publish(ctx, slot, off, n)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        rc, hd = H.hicr_dobj_get_handle(ctx, oid)
+        assert rc == H.OK
+        objs[name] = (oid, hd, n)
+
+    def get_fence(hd):
+        assert H.hicr_dobj_get(ctx, hd, sd, half) == H.OK
+        assert H.hicr_fence(ctx) == H.OK
+
+    dobj = {}
+    for name in ("obj_4KiB_hbm", "obj_4KiB_host"):
+        oid, hd, n = objs[name]
+        lat = []
+        for k in range(550):
+            t0 = time.perf_counter()
+            get_fence(hd)
+            if k >= 50:
+                lat.append((time.perf_counter() - t0) * 1e6)
+        dobj[name] = {"get_fence_p50_us": round(float(np.percentile(lat, 50)), 2),
+                      "get_fence_p99_us": round(float(np.percentile(lat, 99)), 2)}
+    oid, hd, n = objs["obj_half_hbm"]
+    get_fence(hd)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        get_fence(hd)
+    dobj["obj_half_hbm"] = {"bytes": n, "gbps_rw": round(2 * n * reps / (time.perf_counter() - t0) / 1e9, 1)}
+    for oid, _, _ in objs.values():
+        assert H.hicr_dobj_unpublish(ctx, oid) == H.OK
+    out["data_objects"] = dobj
     H.hicr_ctx_destroy(ctx)
     del dev, host
     torch.cuda.empty_cache()
