@@ -333,6 +333,58 @@ namespace hicr {
 // Validate a pump plan whose streams carry resolved addresses, build the
 // device tables and launch.  The caller holds c->mu.  On success the launch
 // is described by *x (event, buffers to free, abort word, channels).
+// A finished pump's buffers with room for `h_bytes` of staging and
+// `d_bytes` on the device, or new ones (rounded up to a power of two, so that
+// pumps of varying size settle on a few buffers).
+static int take_pump_buf(hicr_ctx c, uint64_t h_bytes, uint64_t d_bytes, Extra &x) {
+  for (size_t k = 0; k < c->pump_free.size(); k++) {
+    const PumpBuf &b = c->pump_free[k];
+    if (b.h_cap >= h_bytes && b.d_cap >= d_bytes) {
+      x.h_buf = b.h;
+      x.d_buf = b.d;
+      x.h_cap = b.h_cap;
+      x.d_cap = b.d_cap;
+      c->pump_free.erase(c->pump_free.begin() + (long)k);
+      return HICR_OK;
+    }
+  }
+  auto pow2 = [](uint64_t v) {
+    uint64_t p = 1 << 20;
+    while (p < v) p <<= 1;
+    return p;
+  };
+  const uint64_t hc = pow2(h_bytes), dc = pow2(d_bytes);
+  if (hipHostMalloc(&x.h_buf, hc, hipHostMallocDefault) != hipSuccess) {
+    x.h_buf = nullptr;
+    return fail(c, HICR_ENOMEM, "pump staging (%llu bytes)", (unsigned long long)hc);
+  }
+  if (hipMalloc(&x.d_buf, dc) != hipSuccess) {
+    (void)hipHostFree(x.h_buf);
+    x.h_buf = x.d_buf = nullptr;
+    return fail(c, HICR_ENOMEM, "pump tables (%llu bytes)", (unsigned long long)dc);
+  }
+  x.h_cap = hc;
+  x.d_cap = dc;
+  return HICR_OK;
+}
+
+// Return a pump's buffers for reuse (its launch has completed or never ran);
+// at most 8 are kept, the smallest freed first.
+static void give_pump_buf(hicr_ctx c, Extra &x) {
+  if (!x.h_buf && !x.d_buf) return;
+  c->pump_free.push_back(PumpBuf{x.h_buf, x.d_buf, x.h_cap, x.d_cap});
+  x.h_buf = x.d_buf = nullptr;
+  if (c->pump_free.size() > 8) {
+    auto it = std::min_element(c->pump_free.begin(), c->pump_free.end(),
+                               [](const PumpBuf &a, const PumpBuf &b) {
+                                 return a.h_cap + a.d_cap < b.h_cap + b.d_cap;
+                               });
+    (void)hipFree(it->d);
+    (void)hipHostFree(it->h);
+    c->pump_free.erase(it);
+  }
+}
+
 int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *msg_off,
                 const uint64_t *msg_size, uint64_t n_msgs, uint32_t *trace_dev, uint64_t *ts_dev,
                 uint64_t timeout_ns, hipStream_t s, Extra *xout, bool dev_tables) {
@@ -578,13 +630,8 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
            o_team = upload, total = align(o_team + team_bytes);
   Extra x;
   x.pump = true;
-  hipError_t e = hipHostMalloc(&x.h_buf, upload, hipHostMallocDefault);
-  if (e != hipSuccess) return fail(c, HICR_ENOMEM, "pump staging (%llu bytes)", (unsigned long long)upload);
-  e = hipMalloc(&x.d_buf, total);
-  if (e != hipSuccess) {
-    (void)hipHostFree(x.h_buf);
-    return fail(c, HICR_ENOMEM, "pump tables (%llu bytes)", (unsigned long long)total);
-  }
+  int arc = take_pump_buf(c, upload, total, x);
+  if (arc != HICR_OK) return arc;
   {
     // addresses of the locking teams' scratch, now that the buffer exists
     const uint64_t dbase = reinterpret_cast<uint64_t>(x.d_buf) + o_team;
@@ -624,7 +671,7 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   a.err = reinterpret_cast<uint32_t *>(d + o_err);
   const uint64_t tns = timeout_ns ? timeout_ns : 10'000'000'000ull;
   a.timeout_ticks = tns / 10;  // 100 MHz device clock
-  e = hipMemcpyAsync(d, h, upload, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(d, h, upload, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && team_zero_bytes) e = hipMemsetAsync(d + o_team, 0, team_zero_bytes, s);
   if (e == hipSuccess) e = launch_pump(a, n_wgs, s);
   // error words come back into the (no longer needed) head of the staging
@@ -634,8 +681,7 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(s);
     if (x.ev) (void)hipEventDestroy(x.ev);
-    (void)hipFree(x.d_buf);
-    (void)hipHostFree(x.h_buf);
+    give_pump_buf(c, x);
     return hip_fail(c, e, "launching the channel pump");
   }
   x.abort_word = a.err + 1;
@@ -670,10 +716,17 @@ int pump_finish(hicr_ctx c, Extra &x) {
                          c->abort_words.end());
   }
   (void)hipEventDestroy(x.ev);
-  if (x.d_buf) (void)hipFree(x.d_buf);
-  if (x.h_buf) (void)hipHostFree(x.h_buf);
+  give_pump_buf(c, x);
   x = Extra();
   return rc;
+}
+
+void destroy_pump_bufs(hicr_ctx c) {
+  for (PumpBuf &b : c->pump_free) {
+    if (b.d) (void)hipFree(b.d);
+    if (b.h) (void)hipHostFree(b.h);
+  }
+  c->pump_free.clear();
 }
 
 uint64_t channel_payload_limit(hicr_channel ch) {

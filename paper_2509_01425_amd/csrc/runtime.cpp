@@ -529,6 +529,7 @@ int hicr_ctx_destroy(hicr_ctx c) {
   wait_all(c);
   destroy_plans(c);
   destroy_extra(c);
+  destroy_pump_bufs(c);
   destroy_sched(c);
   destroy_pool(c);
   for (Sub &s : c->subs) {

@@ -61,10 +61,19 @@ struct SchedState;  // autotuned table and device-resident network (sched.cpp)
 
 // Asynchronous work other than copy submissions (channel pushes, pumps):
 // its event, and buffers to free once it has completed.
+// Staging (pinned) and device buffers of a pump launch, reused by later
+// launches once the pump has finished: allocating and freeing them per call
+// cost ~1 ms, and hipFree waits for the device.
+struct PumpBuf {
+  void *h = nullptr, *d = nullptr;
+  uint64_t h_cap = 0, d_cap = 0;
+};
+
 struct Extra {
   hipEvent_t ev = nullptr;
   void *d_buf = nullptr;
   void *h_buf = nullptr;
+  uint64_t h_cap = 0, d_cap = 0;  // sizes of h_buf and d_buf
   bool pump = false;
   uint32_t *abort_word = nullptr;
   std::vector<struct ::hicr_channel_s *> chans;
@@ -100,6 +109,7 @@ struct hicr_ctx_s {
   std::map<uint64_t, hicr_dobj_handle> dobjs;  // published data objects by id
   uint64_t next_dobj_id = 1;
   std::vector<hicr::Extra> extra;
+  std::vector<hicr::PumpBuf> pump_free;  // finished pumps' buffers, for reuse
   int pump_occ = 0;  // pump workgroups per CU
   hipEvent_t push_ev = nullptr;  // last host-API channel push or network step
   bool push_pending = false;
@@ -170,6 +180,7 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
                 const uint64_t *msg_size, uint64_t n_msgs, uint32_t *trace_dev, uint64_t *ts_dev,
                 uint64_t timeout_ns, hipStream_t s, Extra *xout, bool dev_tables = false);
 int pump_finish(hicr_ctx c, Extra &x);
+void destroy_pump_bufs(hicr_ctx c);
 uint64_t channel_payload_limit(struct ::hicr_channel_s *ch);
 int wait_extra(hicr_ctx c);
 bool extra_inflight(hicr_ctx c);
