@@ -363,6 +363,42 @@ def test_rejections_enqueue_nothing(env):
     assert H.hicr_memcpy(ctx, sb, 0, sa, 0, 1) == H.EBADSLOT
 
 
+def test_single_request_over_4gib(env):
+    """One request of 4 GiB + 12,345 bytes at odd offsets (64-bit piece
+    arithmetic: more than 2^32 bytes in one request, a million 4 KiB pieces
+    under class 0), under classes 0 and 9; both ends and sampled windows of
+    the destination, with margins, against the oracle."""
+    torch, H, wd, ctx = env
+    S = (4 << 30) + 12_345
+    D = 3
+    SRC = D + S + (1 << 20) + 5
+    pool_len = SRC + S + 4096
+    seed = 515
+    _say("single request", S, pool_len)
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    rc, sl = H.hicr_slot_register(ctx, pool.data_ptr(), pool_len, H.MEM_HBM)
+    assert rc == H.OK
+    d = np.zeros(1, dtype=H.DESC_DTYPE)
+    d[0] = (sl, sl, D, SRC, S)
+    dabs, sabs, size = np.array([D]), np.array([SRC]), np.array([S])
+    g = np.random.default_rng(8)
+    wins = [(0, 4096 + 64), (D + S - 4096, D + S + 64)] + \
+        [(int(w), int(w) + 4096) for w in g.integers(D, D + S - 4096, 30)]
+    for cls in (0, 9):
+        _say("single request class", cls)
+        wd.fill(pool.data_ptr(), pool_len, seed)
+        torch.cuda.synchronize()
+        assert H.hicr_memcpy_batch(ctx, d, H.hicr_sched_class(cls)[1])[0] == H.OK
+        assert H.hicr_fence(ctx) == H.OK
+        for w0, w1 in wins:
+            want = expected_window(dabs, sabs, size, w0, w1, seed)
+            assert np.array_equal(pool[w0:w1].cpu().numpy(), want), (cls, w0)
+    assert H.hicr_slot_counters(ctx, sl) == (H.OK, 2, 2)
+    assert H.hicr_slot_deregister(ctx, sl) == H.OK
+    del pool
+    torch.cuda.empty_cache()
+
+
 def test_batched_full_size_sampled(env):
     """One batch of the measured configuration (8,192 slot windows over a
     64 GiB + 64 MiB pool, 4,096 requests, ~22 GB) in the launch configuration
