@@ -239,6 +239,68 @@ def test_pump_tiny_fixed_spsc(env):
     assert H.hicr_channel_destroy(ch) == H.OK
 
 
+@pytest.mark.parametrize("mode", ["lock", "nolock"])
+def test_pump_fixed_mpsc_and_spsc(env, mode):
+    """Fixed-size channels through the pump: one MPSC channel of 4 producers
+    and two SPSC channels, 256-byte tokens, 8-token rings, 400 tokens per
+    stream read at scattered token-aligned offsets.  Every stream's output
+    against the oracle (a locking channel's in the merge order its trace
+    records, a non-locking one per producer)."""
+    torch, H, wd, ctx = env
+    C, T, N, K, seed = 8, 256, 400, 4, 97
+    _say("pump fixed", mode)
+    S = K + 2
+    src_bytes = 2 * N * T
+    src = torch.empty(S * src_bytes, dtype=torch.uint8, device="cuda")
+    wd.fill(src.data_ptr(), S * src_bytes, seed)
+    out = torch.zeros(S * N * T, dtype=torch.uint8, device="cuda")
+    rings = K if mode == "nolock" else 1
+    pay = torch.zeros((rings + 2) * C * T, dtype=torch.uint8, device="cuda")
+    ent = torch.zeros((rings + 2) * C, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    hmode = H.CH_MPSC_LOCK if mode == "lock" else H.CH_MPSC_NOLOCK
+    chans = []
+    r0 = 0
+    for nr, m, k in ((rings, hmode, K), (1, H.CH_SPSC, 1), (1, H.CH_SPSC, 1)):
+        ps = _reg(H, ctx, pay, r0 * C * T, nr * C * T)
+        es = _reg(H, ctx, ent, r0 * C * 8, nr * C * 8)
+        rc, ch = H.hicr_channel_create(ctx, H.make_channel_cfg(H.CH_FIXED, m, k, H.CH_DEVICE, ps,
+                                                               es, token_bytes=T, capacity=C))
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        chans.append(ch)
+        r0 += nr
+    g = np.random.default_rng(5)
+    offs = (g.integers(0, src_bytes // T, S * N) * T).astype(np.uint64)
+    sizes = np.full(S * N, T, dtype=np.uint64)
+    streams = []
+    for sidx in range(S):
+        ch, p = (chans[0], sidx) if sidx < K else (chans[sidx - K + 1], 0)
+        ss = _reg(H, ctx, src, sidx * src_bytes, src_bytes)
+        os_ = _reg(H, ctx, out, sidx * N * T, N * T)
+        streams.append((ch, p, ss, os_, sidx * N, N))
+    trace = torch.zeros(S * N, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    assert H.hicr_channel_pump(ctx, streams, offs, sizes, trace.data_ptr(),
+                               timeout_ns=5 * 10**9) == H.OK
+    assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+    host = content(seed, 0, S * src_bytes)
+    msgs = [[host[sidx * src_bytes + int(o):sidx * src_bytes + int(o) + T]
+             for o in offs[sidx * N:(sidx + 1) * N]] for sidx in range(S)]
+    got = out.cpu().numpy().reshape(S, N * T)
+    if mode == "lock":
+        order = [int(x) for x in trace.cpu().numpy()[:K * N]]
+        assert sorted(order) == sorted(list(range(K)) * N)
+        want = oracle_locking_outputs(C * T, C, K, order, msgs[:K])
+    else:
+        want = [oracle_fifo_outputs(C * T, C, msgs[p]) for p in range(K)]
+    for p in range(K):
+        assert np.array_equal(got[p], want[p]), ("producer", p)
+    for sidx in (K, K + 1):
+        assert np.array_equal(got[sidx], oracle_fifo_outputs(C * T, C, msgs[sidx])), sidx
+    for ch in chans:
+        assert H.hicr_channel_destroy(ch) == H.OK
+
+
 def _check_plan(torch, H, rig, plan, seed, mode, trace, sample=None):
     """Compare the pump's outputs with the oracle for every (or sampled) stream."""
     out = rig["out"]
