@@ -295,6 +295,76 @@ def test_large_batch_threaded_checks_and_upload_stream(env):
     assert H.hicr_slot_deregister(ctx, b) == H.OK
 
 
+def test_concurrent_submitters_share_a_context(env):
+    """Four host threads submit 40 batches each (and single memcpys) into one
+    context at once, each into its own destination region; after one fence
+    every byte and both slot counters match the oracle applying the same
+    requests."""
+    import threading
+    torch, H, wd, ctx = env
+    T, B, n = 4, 40, 64
+    region = 1 << 20
+    seed = 61
+    pool_len = (T + 1) * region
+    _say("concurrent submitters")
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), pool_len, seed)
+    torch.cuda.synchronize()
+    rc, dst = H.hicr_slot_register(ctx, pool.data_ptr(), T * region, H.MEM_HBM)
+    rc2, src = H.hicr_slot_register(ctx, pool.data_ptr() + T * region, region, H.MEM_HBM)
+    assert rc == rc2 == H.OK
+    g = np.random.default_rng(12)
+    work = []
+    for t in range(T):
+        batches = []
+        for b in range(B):
+            d = np.zeros(n, dtype=H.DESC_DTYPE)
+            d["dst_slot"], d["src_slot"] = dst, src
+            # request k of batch b writes its own 256-byte cell of the region
+            d["dst_off"] = t * region + (b * n + np.arange(n)) * 256 + g.integers(0, 64, n)
+            d["size"] = g.integers(0, 192, n)
+            d["src_off"] = g.integers(0, region - 256, n)
+            batches.append(d)
+        work.append(batches)
+    errors = []
+
+    def run(t):
+        try:
+            for d in work[t]:
+                assert H.hicr_memcpy_batch(ctx, d)[0] == H.OK
+            d = work[t][0][:1]
+            assert H.hicr_memcpy(ctx, dst, int(d["dst_off"][0]), src, int(d["src_off"][0]),
+                                 int(d["size"][0])) == H.OK
+        except AssertionError as e:
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(t,)) for t in range(T)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors
+    assert H.hicr_fence(ctx) == H.OK
+    host = content(seed, 0, pool_len)
+    oc = oracle.Ctx()
+    od_ = oc.register(host, offset=0, size=T * region)[1]
+    os_ = oc.register(host, offset=T * region, size=region)[1]
+    total = 0
+    for t in range(T):
+        for d in work[t] + [work[t][0][:1]]:
+            od = d.copy()
+            od["dst_slot"], od["src_slot"] = od_, os_
+            assert oc.memcpy_batch(od)[0] == oracle.OK
+            total += len(d)
+    assert np.array_equal(pool.cpu().numpy(), host)
+    assert oc.counters(od_) == (oracle.OK, 0, total)
+    assert oc.counters(os_) == (oracle.OK, total, 0)
+    assert H.hicr_slot_counters(ctx, dst) == (H.OK, 0, total)
+    assert H.hicr_slot_counters(ctx, src) == (H.OK, total, 0)
+    assert H.hicr_slot_deregister(ctx, dst) == H.OK
+    assert H.hicr_slot_deregister(ctx, src) == H.OK
+
+
 def test_single_memcpy_broadcast_and_fence_slot(env):
     """One message copied to many destinations with single memcpy calls and
     one fence (the paper's broadcast example, on one memory space)."""
