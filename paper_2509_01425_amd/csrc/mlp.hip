@@ -1,9 +1,10 @@
 // mlp.hip -- the schedule-predicting network on gfx950: 32 -> 64 -> 64 -> 12,
 // ReLU, softmax cross-entropy, Adam (Kingma & Ba 2015), all fp32.
 //
-// The network is tiny (7,052 parameters, ~14 kFLOP per sample), so each
-// kernel gives one thread one output element and sums in a fixed order: the
-// results are deterministic run to run.  Parameter layout (flat, row-major):
+// The network is tiny (7,052 parameters, ~14 kFLOP per sample): the forward,
+// input-gradient, loss and Adam kernels give one thread one output element,
+// the weight-gradient kernel one workgroup one output unit; every sum runs in
+// a fixed order, so the results are deterministic run to run.  Parameter layout (flat, row-major):
 // W1[64,32] b1[64] W2[64,64] b2[64] W3[12,64] b3[12].
 //
 #include "internal.h"
@@ -57,21 +58,37 @@ __global__ __launch_bounds__(256) void dense_bwd_input_kernel(const float *dY, c
   dX[t] = Xpre[t] > 0.f ? acc : 0.f;
 }
 
-// dW[o,i] = sum_b dY[b,o] X[b,i]; thread (o, I) computes db[o] = sum_b dY[b,o].
+// dW[o,i] = sum_b dY[b,o] X[b,i] and db[o] = sum_b dY[b,o], one workgroup
+// per output o (I <= 256).  256 / I threads share column i, each summing
+// every (256 / I)-th row, so a wavefront reads consecutive columns of a row
+// and every thread keeps many independent loads in flight (one thread per
+// weight walking all B rows left the kernel latency-bound on a few
+// workgroups).  Partial sums meet in LDS in a fixed order: the result does
+// not depend on timing.
 __global__ __launch_bounds__(256) void dense_bwd_weight_kernel(const float *dY, const float *X,
                                                                int I, int O, int B, float *dW,
                                                                float *db) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= O * (I + 1)) return;
-  const int o = t / (I + 1), i = t % (I + 1);
+  __shared__ float part[256];
+  __shared__ float wsum[4];
+  const int o = blockIdx.x, t = threadIdx.x;
+  const int parts = 256 / I, i = t % I, p = t / I;
   float acc = 0.f;
-  if (i < I) {
-    for (int b = 0; b < B; b++) acc = fmaf(dY[b * O + o], X[b * I + i], acc);
-    dW[o * I + i] = acc;
-  } else {
-    for (int b = 0; b < B; b++) acc += dY[b * O + o];
-    db[o] = acc;
+  if (p < parts) {
+#pragma unroll 16
+    for (int b = p; b < B; b += parts) acc = fmaf(dY[b * O + o], X[b * I + i], acc);
   }
+  part[t] = acc;
+  float bs = 0.f;
+  for (int b = t; b < B; b += 256) bs += dY[b * O + o];
+  for (int off = 32; off > 0; off >>= 1) bs += __shfl_down(bs, off, 64);
+  if ((t & 63) == 0) wsum[t >> 6] = bs;
+  __syncthreads();
+  if (t < I) {
+    float sum = 0.f;
+    for (int q = 0; q < parts; q++) sum += part[q * I + t];
+    dW[o * I + t] = sum;
+  }
+  if (t == 0) db[o] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
 __global__ __launch_bounds__(256) void mean_kernel(const float *v, int n, float *out) {
@@ -100,6 +117,8 @@ __global__ __launch_bounds__(256) void adam_kernel(float *p, const float *g, flo
   p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
+static_assert(kMlpIn <= 256 && kMlpHidden <= 256, "dense_bwd_weight_kernel spreads I columns over 256 threads");
+
 static inline unsigned blocks(int n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t mlp_forward(const MlpBufs &m, const float *params, const float *X, int B,
@@ -125,15 +144,15 @@ hipError_t mlp_backward(const MlpBufs &m, const float *params, const float *X, c
         *gb3 = gW3 + kMlpOut * kMlpHidden;
   hipLaunchKernelGGL(softmax_xent_kernel, dim3(blocks(B)), dim3(256), 0, s, m.z, y, B, m.dz,
                      m.loss);
-  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(blocks(kMlpOut * (kMlpHidden + 1))), dim3(256),
+  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(kMlpOut), dim3(256),
                      0, s, m.dz, m.h2, kMlpHidden, kMlpOut, B, gW3, gb3);
   hipLaunchKernelGGL(dense_bwd_input_kernel, dim3(blocks(B * kMlpHidden)), dim3(256), 0, s, m.dz,
                      W3, m.a2, kMlpHidden, kMlpOut, B, m.d2);
-  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(blocks(kMlpHidden * (kMlpHidden + 1))),
-                     dim3(256), 0, s, m.d2, m.h1, kMlpHidden, kMlpHidden, B, gW2, gb2);
+  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(kMlpHidden), dim3(256), 0, s, m.d2, m.h1,
+                     kMlpHidden, kMlpHidden, B, gW2, gb2);
   hipLaunchKernelGGL(dense_bwd_input_kernel, dim3(blocks(B * kMlpHidden)), dim3(256), 0, s, m.d2,
                      W2, m.a1, kMlpHidden, kMlpHidden, B, m.d1);
-  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(blocks(kMlpHidden * (kMlpIn + 1))), dim3(256),
+  hipLaunchKernelGGL(dense_bwd_weight_kernel, dim3(kMlpHidden), dim3(256),
                      0, s, m.d1, X, kMlpIn, kMlpHidden, B, gW1, gb1);
   if (loss_mean) hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, m.loss, B, loss_mean);
   return hipGetLastError();
