@@ -12,16 +12,38 @@
 
 namespace hicr {
 
+// Y[b,o] = bias[o] + sum_i W[o,i] X[b,i], summed from the bias in ascending
+// i (the host inference uses the same order); Yact gets the ReLU.  A
+// workgroup takes 256 / O samples and stages W transposed (rows padded to
+// O + 1, so neither the staging stores nor the loop's reads conflict in LDS)
+// and its samples' inputs: lanes then read consecutive W^T entries, where
+// reading row-major W directly was a stride-I access in every lane.
+constexpr int kFwdWords = kMlpHidden * (kMlpHidden + 1);
+constexpr int kFwdInputs = 2048;
+static_assert(kMlpIn * (kMlpHidden + 1) <= kFwdWords && kMlpHidden * (kMlpOut + 1) <= kFwdWords,
+              "every layer's W^T fits the LDS stage");
+static_assert((256 / kMlpHidden) * kMlpHidden <= kFwdInputs &&
+                  (256 / kMlpOut) * kMlpHidden <= kFwdInputs,
+              "every layer's sample inputs fit the LDS stage");
 __global__ __launch_bounds__(256) void dense_fwd_kernel(const float *X, const float *W,
                                                         const float *bias, int I, int O, int B,
                                                         float *Ypre, float *Yact) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= B * O) return;
-  const int b = t / O, o = t % O;
+  __shared__ float wt[kFwdWords];
+  __shared__ float xs[kFwdInputs];
+  const int t = threadIdx.x, S = 256 / O, P = O + 1;
+  const int b0 = blockIdx.x * S;
+  const int nS = B - b0 < S ? B - b0 : S;
+  for (int k = t; k < I * O; k += 256) wt[(k % I) * P + k / I] = W[k];
+  for (int k = t; k < nS * I; k += 256) xs[k] = X[b0 * I + k];
+  __syncthreads();
+  const int sm = t / O, o = t % O;
+  if (sm >= nS) return;
   float acc = bias[o];
-  for (int i = 0; i < I; i++) acc = fmaf(W[o * I + i], X[b * I + i], acc);
-  Ypre[t] = acc;
-  if (Yact) Yact[t] = acc > 0.f ? acc : 0.f;
+#pragma unroll 8
+  for (int i = 0; i < I; i++) acc = fmaf(wt[i * P + o], xs[sm * I + i], acc);
+  const int y = (b0 + sm) * O + o;
+  Ypre[y] = acc;
+  if (Yact) Yact[y] = acc > 0.f ? acc : 0.f;
 }
 
 // Per sample: softmax of the logits, dZ = (p - onehot(y)) / B, and the
@@ -54,6 +76,7 @@ __global__ __launch_bounds__(256) void dense_bwd_input_kernel(const float *dY, c
   if (t >= B * I) return;
   const int b = t / I, i = t % I;
   float acc = 0.f;
+#pragma unroll 16
   for (int o = 0; o < O; o++) acc = fmaf(dY[b * O + o], W[o * I + i], acc);
   dX[t] = Xpre[t] > 0.f ? acc : 0.f;
 }
@@ -120,17 +143,19 @@ __global__ __launch_bounds__(256) void adam_kernel(float *p, const float *g, flo
 static_assert(kMlpIn <= 256 && kMlpHidden <= 256, "dense_bwd_weight_kernel spreads I columns over 256 threads");
 
 static inline unsigned blocks(int n) { return (unsigned)((n + 255) / 256); }
+// workgroups of dense_fwd_kernel: 256 / O samples each
+static inline unsigned fwd_blocks(int B, int O) { return (unsigned)((B + 256 / O - 1) / (256 / O)); }
 
 hipError_t mlp_forward(const MlpBufs &m, const float *params, const float *X, int B,
                        hipStream_t s) {
   const float *W1 = params, *b1 = W1 + kMlpHidden * kMlpIn, *W2 = b1 + kMlpHidden,
               *b2 = W2 + kMlpHidden * kMlpHidden, *W3 = b2 + kMlpHidden,
               *b3 = W3 + kMlpOut * kMlpHidden;
-  hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks(B * kMlpHidden)), dim3(256), 0, s, X, W1, b1,
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(fwd_blocks(B, kMlpHidden)), dim3(256), 0, s, X, W1, b1,
                      kMlpIn, kMlpHidden, B, m.a1, m.h1);
-  hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks(B * kMlpHidden)), dim3(256), 0, s, m.h1, W2,
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(fwd_blocks(B, kMlpHidden)), dim3(256), 0, s, m.h1, W2,
                      b2, kMlpHidden, kMlpHidden, B, m.a2, m.h2);
-  hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks(B * kMlpOut)), dim3(256), 0, s, m.h2, W3, b3,
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(fwd_blocks(B, kMlpOut)), dim3(256), 0, s, m.h2, W3, b3,
                      kMlpHidden, kMlpOut, B, m.z, (float *)nullptr);
   return hipGetLastError();
 }
