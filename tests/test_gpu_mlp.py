@@ -189,6 +189,43 @@ def test_learned_submission_picks_oracle_class_and_moves_bytes(env):
 
 
 
+def test_device_forward_argmax_equals_host_choice(env):
+    """The learned submission infers on the host; the device forward kernel
+    sums every layer in the same order with fused multiply-adds, so for any
+    parameters the argmax of the device logits is the host's class.  Checked
+    with unbiased random parameters on 40 random subsets of a hazard-free
+    batch (random request counts give varied features)."""
+    torch, H, ctx = env
+    bases, sizes, pool_len, descs, _ = wm.tiny(5)
+    pool = torch.empty(pool_len, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    slots = np.array([H.hicr_slot_register(ctx, pool.data_ptr() + int(b), int(s))[1]
+                      for b, s in zip(bases, sizes)], dtype=np.uint32)
+    d_all = descs.copy()
+    d_all["dst_slot"], d_all["src_slot"] = slots[descs["dst_slot"]], slots[descs["src_slot"]]
+    theta = he_uniform(300).astype(np.float32)
+    assert H.hicr_mlp_set_params(ctx, theta) == H.OK
+    g = np.random.default_rng(17)
+    x = torch.empty(1, 32, dtype=torch.float32, device="cuda")
+    z = torch.empty(1, 12, dtype=torch.float32, device="cuda")
+    for _ in range(40):
+        k = int(g.integers(1, len(d_all) + 1))
+        d = d_all[np.sort(g.choice(len(d_all), size=k, replace=False))]
+        rc, _ = H.hicr_memcpy_batch(ctx, d, H.make_sched(65536, 1, 2, H.SCHED_LEARNED))
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        assert H.hicr_fence(ctx) == H.OK
+        rc, cls = H.hicr_last_choice(ctx)
+        assert rc == H.OK
+        rc, f = H.hicr_sched_features(d)
+        assert rc == H.OK
+        x.copy_(torch.from_numpy(f).reshape(1, 32))
+        torch.cuda.synchronize()
+        assert H.hicr_mlp_forward(ctx, x.data_ptr(), 1, z.data_ptr()) == H.OK
+        assert int(torch.argmax(z.cpu()[0])) == cls, (k, cls, z.cpu()[0])
+    for s in slots:
+        assert H.hicr_slot_deregister(ctx, int(s)) == H.OK
+
+
 def test_tuned_table_lookup_is_the_nearest_feature(env):
     """The tuned table's choice equals a brute-force nearest neighbour over
     the oracle's features (first minimum on ties); an empty table is an
