@@ -22,11 +22,13 @@
  *
  * General conventions
  *   - Every function returns 0 (HICR_OK) or a negative HICR_E* code and never
- *     throws.  hicr_last_error() gives a human-readable reason for the last
- *     failure on a context.
+ *     throws: a host allocation that fails inside a call returns
+ *     HICR_ENOMEM.  hicr_last_error() gives a human-readable reason for the
+ *     last failure on a context.
  *   - Pointers named *_dev are device (HBM) addresses; all other pointers are
- *     host addresses (a slot's own memory may be HBM or pinned host memory).  "stream" arguments are hipStream_t values passed as
- *     void*; NULL selects the context's own stream.
+ *     host addresses (a slot's own memory may be HBM or pinned host memory).
+ *     "stream" arguments are hipStream_t values passed as void*; NULL selects
+ *     the context's own stream.
  *   - The caller owns every registered allocation and must keep it alive
  *     until the slot is deregistered.  The library owns its internal buffers.
  *   - Transfers are asynchronous: a successful return means the request was

@@ -141,189 +141,201 @@ void destroy_extra(hicr_ctx c) {
 extern "C" {
 
 int hicr_channel_create(hicr_ctx c, const hicr_channel_cfg *cfg, hicr_channel *out) {
-  if (!c || !cfg || !out) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  *out = nullptr;
-  const hicr_channel_cfg &k = *cfg;
-  if (k.kind != HICR_CH_FIXED && k.kind != HICR_CH_VAR) return fail(c, HICR_EINVAL, "bad kind");
-  if (k.mode > HICR_CH_MPSC_NOLOCK) return fail(c, HICR_EINVAL, "bad mode");
-  if (k.endpoints != HICR_CH_HOST && k.endpoints != HICR_CH_DEVICE)
-    return fail(c, HICR_EINVAL, "bad endpoints");
-  if (k.mode == HICR_CH_SPSC ? k.producers != 1
-                             : (k.producers < 1 || k.producers > HICR_CH_MAX_PRODUCERS))
-    return fail(c, HICR_EINVAL, "producers %u not valid for the mode", k.producers);
-  uint64_t P, E;
-  if (k.kind == HICR_CH_FIXED) {
-    if (k.token_bytes == 0 || k.capacity == 0 || k.capacity > (1ull << 40) / k.token_bytes)
-      return fail(c, HICR_EINVAL, "fixed channel needs token_bytes > 0 and capacity > 0");
-    P = k.capacity * k.token_bytes;
-    E = k.capacity;
-  } else {
-    if (k.capacity == 0 || k.entries == 0 || k.capacity > kEntrySizeMask || k.entries > (1ull << 40))
-      return fail(c, HICR_EINVAL, "variable channel needs capacity > 0 and entries > 0");
-    P = k.capacity;
-    E = k.entries;
-  }
-  const uint32_t rings = k.mode == HICR_CH_MPSC_NOLOCK ? k.producers : 1;
-  int rc = check_hbm_slot(c, k.payload, rings * P, "payload");
-  if (rc != HICR_OK) return rc;
-  rc = check_hbm_slot(c, k.entries_slot, rings * E * 8, "entries");
-  if (rc != HICR_OK) return rc;
-  if (c->slots[k.entries_slot].base % 8) return fail(c, HICR_EINVAL, "entries slot not 8-byte aligned");
-  hicr_channel ch = new (std::nothrow) hicr_channel_s();
-  if (!ch) return HICR_ENOMEM;
-  ch->ctx = c;
-  ch->cfg = k;
-  ch->n_rings = rings;
-  ch->P = P;
-  ch->E = E;
-  ch->payload_base = c->slots[k.payload].base;
-  ch->entries_base = c->slots[k.entries_slot].base;
-  const size_t bytes = sizeof(RingCoord) * rings;
-  hipError_t e;
-  if (k.endpoints == HICR_CH_HOST) {
-    void *h = nullptr;
-    e = hipHostMalloc(&h, bytes, hipHostMallocCoherent | hipHostMallocMapped);
-    if (e == hipSuccess) {
-      std::memset(h, 0, bytes);
-      ch->coord_host = static_cast<RingCoord *>(h);
-      void *d = nullptr;
-      e = hipHostGetDevicePointer(&d, h, 0);
-      ch->coord_dev = static_cast<RingCoord *>(d);
+  return guarded([&]() -> int {
+    if (!c || !cfg || !out) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    *out = nullptr;
+    const hicr_channel_cfg &k = *cfg;
+    if (k.kind != HICR_CH_FIXED && k.kind != HICR_CH_VAR) return fail(c, HICR_EINVAL, "bad kind");
+    if (k.mode > HICR_CH_MPSC_NOLOCK) return fail(c, HICR_EINVAL, "bad mode");
+    if (k.endpoints != HICR_CH_HOST && k.endpoints != HICR_CH_DEVICE)
+      return fail(c, HICR_EINVAL, "bad endpoints");
+    if (k.mode == HICR_CH_SPSC ? k.producers != 1
+                               : (k.producers < 1 || k.producers > HICR_CH_MAX_PRODUCERS))
+      return fail(c, HICR_EINVAL, "producers %u not valid for the mode", k.producers);
+    uint64_t P, E;
+    if (k.kind == HICR_CH_FIXED) {
+      if (k.token_bytes == 0 || k.capacity == 0 || k.capacity > (1ull << 40) / k.token_bytes)
+        return fail(c, HICR_EINVAL, "fixed channel needs token_bytes > 0 and capacity > 0");
+      P = k.capacity * k.token_bytes;
+      E = k.capacity;
+    } else {
+      if (k.capacity == 0 || k.entries == 0 || k.capacity > kEntrySizeMask || k.entries > (1ull << 40))
+        return fail(c, HICR_EINVAL, "variable channel needs capacity > 0 and entries > 0");
+      P = k.capacity;
+      E = k.entries;
     }
-    ch->rh.resize(rings);
-    for (auto &r : ch->rh) r.ent.assign(E, 0);
-  } else {
-    void *d = nullptr;
-    e = hipMalloc(&d, bytes);
-    if (e == hipSuccess) e = hipMemset(d, 0, bytes);
-    ch->coord_dev = static_cast<RingCoord *>(d);
-    ch->dev_msgs.assign(rings, 0);
-  }
-  if (e != hipSuccess) {
-    free_channel(ch);
-    return fail(c, HICR_ENOMEM, "coordination counters: %s", hipGetErrorString(e));
-  }
-  c->channels.push_back(ch);
-  *out = ch;
-  return HICR_OK;
+    const uint32_t rings = k.mode == HICR_CH_MPSC_NOLOCK ? k.producers : 1;
+    int rc = check_hbm_slot(c, k.payload, rings * P, "payload");
+    if (rc != HICR_OK) return rc;
+    rc = check_hbm_slot(c, k.entries_slot, rings * E * 8, "entries");
+    if (rc != HICR_OK) return rc;
+    if (c->slots[k.entries_slot].base % 8) return fail(c, HICR_EINVAL, "entries slot not 8-byte aligned");
+    hicr_channel ch = new (std::nothrow) hicr_channel_s();
+    if (!ch) return HICR_ENOMEM;
+    ch->ctx = c;
+    ch->cfg = k;
+    ch->n_rings = rings;
+    ch->P = P;
+    ch->E = E;
+    ch->payload_base = c->slots[k.payload].base;
+    ch->entries_base = c->slots[k.entries_slot].base;
+    const size_t bytes = sizeof(RingCoord) * rings;
+    hipError_t e;
+    if (k.endpoints == HICR_CH_HOST) {
+      void *h = nullptr;
+      e = hipHostMalloc(&h, bytes, hipHostMallocCoherent | hipHostMallocMapped);
+      if (e == hipSuccess) {
+        std::memset(h, 0, bytes);
+        ch->coord_host = static_cast<RingCoord *>(h);
+        void *d = nullptr;
+        e = hipHostGetDevicePointer(&d, h, 0);
+        ch->coord_dev = static_cast<RingCoord *>(d);
+      }
+      ch->rh.resize(rings);
+      for (auto &r : ch->rh) r.ent.assign(E, 0);
+    } else {
+      void *d = nullptr;
+      e = hipMalloc(&d, bytes);
+      if (e == hipSuccess) e = hipMemset(d, 0, bytes);
+      ch->coord_dev = static_cast<RingCoord *>(d);
+      ch->dev_msgs.assign(rings, 0);
+    }
+    if (e != hipSuccess) {
+      free_channel(ch);
+      return fail(c, HICR_ENOMEM, "coordination counters: %s", hipGetErrorString(e));
+    }
+    c->channels.push_back(ch);
+    *out = ch;
+    return HICR_OK;
+  });
 }
 
 int hicr_channel_destroy(hicr_channel ch) {
-  if (!ch) return HICR_EINVAL;
-  hicr_ctx c = ch->ctx;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!registered(c, ch)) return HICR_EINVAL;
-  (void)hipSetDevice(c->device);
-  int rc = wait_all(c);
-  c->channels.erase(std::find(c->channels.begin(), c->channels.end(), ch));
-  free_channel(ch);
-  return rc;
+  return guarded([&]() -> int {
+    if (!ch) return HICR_EINVAL;
+    hicr_ctx c = ch->ctx;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!registered(c, ch)) return HICR_EINVAL;
+    (void)hipSetDevice(c->device);
+    int rc = wait_all(c);
+    c->channels.erase(std::find(c->channels.begin(), c->channels.end(), ch));
+    free_channel(ch);
+    return rc;
+  });
 }
 
 int hicr_channel_push(hicr_channel ch, uint32_t producer, hicr_slot src, uint64_t src_off,
                       uint64_t count) {
-  if (!ch) return HICR_EINVAL;
-  hicr_ctx c = ch->ctx;
-  std::lock_guard<std::mutex> g(c->mu);  // the producers' exclusive access
-  if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
-  if (producer >= ch->cfg.producers) return fail(c, HICR_EINVAL, "no producer %u", producer);
-  const bool fixed = ch->cfg.kind == HICR_CH_FIXED;
-  uint64_t bytes, n_ent, ent_bytes;
-  if (fixed) {
-    if (count > ch->cfg.capacity) return fail(c, HICR_EINVAL, "more tokens than the ring holds");
-    bytes = count * ch->cfg.token_bytes;
-    n_ent = count;
-    ent_bytes = ch->cfg.token_bytes;
-  } else {
-    if (count > ch->P) return fail(c, HICR_EINVAL, "message larger than the ring");
-    bytes = count;
-    n_ent = 1;
-    ent_bytes = count;
-  }
-  if (src >= c->slots.size() || !c->slots[src].live) return fail(c, HICR_EBADSLOT, "bad source slot");
-  const Slot &ss = c->slots[src];
-  if (ss.space != HICR_MEM_HBM) return fail(c, HICR_EUNSUPPORTED, "source not in HBM");
-  if (src_off > ss.size || bytes > ss.size - src_off) return fail(c, HICR_ERANGE, "source range");
-  const uint32_t r = ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? producer : 0;
-  auto &h = ch->rh[r];
-  const uint64_t hm = __atomic_load_n(&ch->coord_host[r].cons.w[0], __ATOMIC_ACQUIRE);
-  const uint64_t hb = __atomic_load_n(&ch->coord_host[r].cons.w[1], __ATOMIC_ACQUIRE);
-  if ((h.tm - hm) + n_ent > ch->E || (h.tb - hb) + bytes > ch->P)
-    return HICR_EAGAIN;  // full: the consumer has not released enough room
-  if (n_ent == 0) return HICR_OK;
-  (void)hipSetDevice(c->device);
-  PushArgs pa;
-  pa.ring = dev_ring(ch, r);
-  pa.src = ss.base + src_off;
-  pa.bytes = bytes;
-  pa.pos = h.tb % ch->P;
-  pa.first_entry = h.tm;
-  pa.n_entries = (uint32_t)n_ent;
-  pa.producer = producer;
-  pa.entry_bytes = ent_bytes;
-  pa.publish = &ch->coord_dev[r].prod.w[0];
-  pa.publish_value = h.tm + n_ent;
-  hipError_t e = launch_push(pa, c->stream);
-  if (e == hipSuccess) e = hipEventRecord(c->push_ev, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "launching a channel push");
-  c->push_pending = true;
-  for (uint64_t i = 0; i < n_ent; i++)
-    h.ent[(h.tm + i) % ch->E] = ent_bytes | ((uint64_t)producer << 48);
-  h.tm += n_ent;
-  h.tb += bytes;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!ch) return HICR_EINVAL;
+    hicr_ctx c = ch->ctx;
+    std::lock_guard<std::mutex> g(c->mu);  // the producers' exclusive access
+    if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
+    if (producer >= ch->cfg.producers) return fail(c, HICR_EINVAL, "no producer %u", producer);
+    const bool fixed = ch->cfg.kind == HICR_CH_FIXED;
+    uint64_t bytes, n_ent, ent_bytes;
+    if (fixed) {
+      if (count > ch->cfg.capacity) return fail(c, HICR_EINVAL, "more tokens than the ring holds");
+      bytes = count * ch->cfg.token_bytes;
+      n_ent = count;
+      ent_bytes = ch->cfg.token_bytes;
+    } else {
+      if (count > ch->P) return fail(c, HICR_EINVAL, "message larger than the ring");
+      bytes = count;
+      n_ent = 1;
+      ent_bytes = count;
+    }
+    if (src >= c->slots.size() || !c->slots[src].live) return fail(c, HICR_EBADSLOT, "bad source slot");
+    const Slot &ss = c->slots[src];
+    if (ss.space != HICR_MEM_HBM) return fail(c, HICR_EUNSUPPORTED, "source not in HBM");
+    if (src_off > ss.size || bytes > ss.size - src_off) return fail(c, HICR_ERANGE, "source range");
+    const uint32_t r = ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? producer : 0;
+    auto &h = ch->rh[r];
+    const uint64_t hm = __atomic_load_n(&ch->coord_host[r].cons.w[0], __ATOMIC_ACQUIRE);
+    const uint64_t hb = __atomic_load_n(&ch->coord_host[r].cons.w[1], __ATOMIC_ACQUIRE);
+    if ((h.tm - hm) + n_ent > ch->E || (h.tb - hb) + bytes > ch->P)
+      return HICR_EAGAIN;  // full: the consumer has not released enough room
+    if (n_ent == 0) return HICR_OK;
+    (void)hipSetDevice(c->device);
+    PushArgs pa;
+    pa.ring = dev_ring(ch, r);
+    pa.src = ss.base + src_off;
+    pa.bytes = bytes;
+    pa.pos = h.tb % ch->P;
+    pa.first_entry = h.tm;
+    pa.n_entries = (uint32_t)n_ent;
+    pa.producer = producer;
+    pa.entry_bytes = ent_bytes;
+    pa.publish = &ch->coord_dev[r].prod.w[0];
+    pa.publish_value = h.tm + n_ent;
+    hipError_t e = launch_push(pa, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->push_ev, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "launching a channel push");
+    c->push_pending = true;
+    for (uint64_t i = 0; i < n_ent; i++)
+      h.ent[(h.tm + i) % ch->E] = ent_bytes | ((uint64_t)producer << 48);
+    h.tm += n_ent;
+    h.tb += bytes;
+    return HICR_OK;
+  });
 }
 
 int hicr_channel_peek(hicr_channel ch, uint32_t ring, uint64_t i, uint64_t *payload_off,
                       uint64_t *bytes, uint32_t *producer) {
-  if (!ch) return HICR_EINVAL;
-  hicr_ctx c = ch->ctx;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
-  if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
-  auto &h = ch->rh[ring];
-  const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
-  if (i >= tm - h.hm) return HICR_EAGAIN;
-  uint64_t off = h.hb;
-  for (uint64_t k = 0; k < i; k++) off += entry_size(h.ent[(h.hm + k) % ch->E]);
-  const uint64_t e = h.ent[(h.hm + i) % ch->E];
-  if (payload_off) *payload_off = ring * ch->P + off % ch->P;
-  if (bytes) *bytes = entry_size(e);
-  if (producer) *producer = (uint32_t)(e >> 48);
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!ch) return HICR_EINVAL;
+    hicr_ctx c = ch->ctx;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
+    if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
+    auto &h = ch->rh[ring];
+    const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
+    if (i >= tm - h.hm) return HICR_EAGAIN;
+    uint64_t off = h.hb;
+    for (uint64_t k = 0; k < i; k++) off += entry_size(h.ent[(h.hm + k) % ch->E]);
+    const uint64_t e = h.ent[(h.hm + i) % ch->E];
+    if (payload_off) *payload_off = ring * ch->P + off % ch->P;
+    if (bytes) *bytes = entry_size(e);
+    if (producer) *producer = (uint32_t)(e >> 48);
+    return HICR_OK;
+  });
 }
 
 int hicr_channel_pop(hicr_channel ch, uint32_t ring, uint64_t n) {
-  if (!ch) return HICR_EINVAL;
-  hicr_ctx c = ch->ctx;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
-  if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
-  auto &h = ch->rh[ring];
-  const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
-  if (n > tm - h.hm) return HICR_EAGAIN;
-  for (uint64_t k = 0; k < n; k++) h.hb += entry_size(h.ent[(h.hm + k) % ch->E]);
-  h.hm += n;
-  __atomic_store_n(&ch->coord_host[ring].cons.w[1], h.hb, __ATOMIC_RELEASE);
-  __atomic_store_n(&ch->coord_host[ring].cons.w[0], h.hm, __ATOMIC_RELEASE);
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!ch) return HICR_EINVAL;
+    hicr_ctx c = ch->ctx;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
+    if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
+    auto &h = ch->rh[ring];
+    const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
+    if (n > tm - h.hm) return HICR_EAGAIN;
+    for (uint64_t k = 0; k < n; k++) h.hb += entry_size(h.ent[(h.hm + k) % ch->E]);
+    h.hm += n;
+    __atomic_store_n(&ch->coord_host[ring].cons.w[1], h.hb, __ATOMIC_RELEASE);
+    __atomic_store_n(&ch->coord_host[ring].cons.w[0], h.hm, __ATOMIC_RELEASE);
+    return HICR_OK;
+  });
 }
 
 int hicr_channel_depth(hicr_channel ch, uint32_t ring, uint64_t *msgs, uint64_t *bytes) {
-  if (!ch) return HICR_EINVAL;
-  hicr_ctx c = ch->ctx;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
-  if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
-  auto &h = ch->rh[ring];
-  const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
-  uint64_t b = 0;
-  for (uint64_t k = h.hm; k < tm; k++) b += entry_size(h.ent[k % ch->E]);
-  if (msgs) *msgs = tm - h.hm;
-  if (bytes) *bytes = b;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!ch) return HICR_EINVAL;
+    hicr_ctx c = ch->ctx;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (ch->cfg.endpoints != HICR_CH_HOST) return fail(c, HICR_EINVAL, "device-endpoint channel");
+    if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
+    auto &h = ch->rh[ring];
+    const uint64_t tm = __atomic_load_n(&ch->coord_host[ring].prod.w[0], __ATOMIC_ACQUIRE);
+    uint64_t b = 0;
+    for (uint64_t k = h.hm; k < tm; k++) b += entry_size(h.ent[k % ch->E]);
+    if (msgs) *msgs = tm - h.hm;
+    if (bytes) *bytes = b;
+    return HICR_OK;
+  });
 }
 
 }  // extern "C"
@@ -739,66 +751,72 @@ extern "C" {
 
 int hicr_channel_pump(hicr_ctx c, const hicr_stream *st, uint32_t n, const hicr_pump_io *io,
                       void *stream) {
-  if (!c || !io || (n && !st) || (io->flags & ~HICR_PUMP_DEVICE_TABLES) || io->reserved)
-    return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  std::vector<PumpStream> ps(n);
-  for (uint32_t i = 0; i < n; i++) {
-    int rc = check_hbm_slot(c, st[i].src, 1, "stream source");
-    if (rc != HICR_OK) return rc;
-    rc = check_hbm_slot(c, st[i].out, 1, "stream output");
-    if (rc != HICR_OK) return rc;
-    ps[i].channel = st[i].channel;
-    ps[i].producer = st[i].producer;
-    ps[i].src_base = c->slots[st[i].src].base;
-    ps[i].src_size = c->slots[st[i].src].size;
-    ps[i].out_base = c->slots[st[i].out].base;
-    ps[i].out_size = c->slots[st[i].out].size;
-    ps[i].first_msg = st[i].first_msg;
-    ps[i].n_msgs = st[i].n_msgs;
-  }
-  Extra x;
-  int rc = pump_launch(c, ps, io->msg_src_off, io->msg_size, io->n_msgs, io->trace_dev,
-                       io->ts_dev, io->timeout_ns,
-                       stream ? static_cast<hipStream_t>(stream) : c->stream, &x,
-                       (io->flags & HICR_PUMP_DEVICE_TABLES) != 0);
-  if (rc == HICR_OK && x.ev) c->extra.push_back(x);
-  return rc;
+  return guarded([&]() -> int {
+    if (!c || !io || (n && !st) || (io->flags & ~HICR_PUMP_DEVICE_TABLES) || io->reserved)
+      return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    std::vector<PumpStream> ps(n);
+    for (uint32_t i = 0; i < n; i++) {
+      int rc = check_hbm_slot(c, st[i].src, 1, "stream source");
+      if (rc != HICR_OK) return rc;
+      rc = check_hbm_slot(c, st[i].out, 1, "stream output");
+      if (rc != HICR_OK) return rc;
+      ps[i].channel = st[i].channel;
+      ps[i].producer = st[i].producer;
+      ps[i].src_base = c->slots[st[i].src].base;
+      ps[i].src_size = c->slots[st[i].src].size;
+      ps[i].out_base = c->slots[st[i].out].base;
+      ps[i].out_size = c->slots[st[i].out].size;
+      ps[i].first_msg = st[i].first_msg;
+      ps[i].n_msgs = st[i].n_msgs;
+    }
+    Extra x;
+    int rc = pump_launch(c, ps, io->msg_src_off, io->msg_size, io->n_msgs, io->trace_dev,
+                         io->ts_dev, io->timeout_ns,
+                         stream ? static_cast<hipStream_t>(stream) : c->stream, &x,
+                         (io->flags & HICR_PUMP_DEVICE_TABLES) != 0);
+    if (rc == HICR_OK && x.ev) c->extra.push_back(x);
+    return rc;
+  });
 }
 
 int hicr_channel_device_view(hicr_channel ch, uint32_t ring, hicr_dev_ring *out) {
-  if (!ch || !out) return HICR_EINVAL;
-  hicr_ctx c = ch->ctx;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!registered(c, ch)) return HICR_EINVAL;
-  if (ch->cfg.endpoints != HICR_CH_DEVICE) return fail(c, HICR_EINVAL, "host-endpoint channel");
-  if (ch->cfg.mode == HICR_CH_MPSC_LOCK)
-    return fail(c, HICR_EUNSUPPORTED, "locking MPSC rings are driven by the pump only");
-  if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
-  if (ch->broken) return fail(c, HICR_EINVAL, "channel broken by an earlier error");
-  const DevRing r = dev_ring(ch, ring);
-  out->payload = r.payload;
-  out->P = r.P;
-  out->entries = r.entries;
-  out->E = r.E;
-  out->coord = r.coord;
-  out->producer = ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? ring : 0;
-  out->pad = 0;
-  ch->user_kernels = true;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!ch || !out) return HICR_EINVAL;
+    hicr_ctx c = ch->ctx;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!registered(c, ch)) return HICR_EINVAL;
+    if (ch->cfg.endpoints != HICR_CH_DEVICE) return fail(c, HICR_EINVAL, "host-endpoint channel");
+    if (ch->cfg.mode == HICR_CH_MPSC_LOCK)
+      return fail(c, HICR_EUNSUPPORTED, "locking MPSC rings are driven by the pump only");
+    if (ring >= ch->n_rings) return fail(c, HICR_EINVAL, "no ring %u", ring);
+    if (ch->broken) return fail(c, HICR_EINVAL, "channel broken by an earlier error");
+    const DevRing r = dev_ring(ch, ring);
+    out->payload = r.payload;
+    out->P = r.P;
+    out->entries = r.entries;
+    out->E = r.E;
+    out->coord = r.coord;
+    out->producer = ch->cfg.mode == HICR_CH_MPSC_NOLOCK ? ring : 0;
+    out->pad = 0;
+    ch->user_kernels = true;
+    return HICR_OK;
+  });
 }
 
 int hicr_channel_abort(hicr_ctx c) {
-  if (!c) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->abort_mu);  // not c->mu: a fence may hold it
-  (void)hipSetDevice(c->device);
-  static const uint32_t one = 1;
-  for (uint32_t *w : c->abort_words) {
-    hipError_t e = hipMemcpyAsync(w, &one, 4, hipMemcpyHostToDevice, c->abort_stream);
-    if (e != hipSuccess) return fail(nullptr, HICR_EDEVICE, "abort");
-  }
-  return hipStreamSynchronize(c->abort_stream) == hipSuccess ? HICR_OK : HICR_EDEVICE;
+  return guarded([&]() -> int {
+    if (!c) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->abort_mu);  // not c->mu: a fence may hold it
+    (void)hipSetDevice(c->device);
+    static const uint32_t one = 1;
+    for (uint32_t *w : c->abort_words) {
+      hipError_t e = hipMemcpyAsync(w, &one, 4, hipMemcpyHostToDevice, c->abort_stream);
+      if (e != hipSuccess) return fail(nullptr, HICR_EDEVICE, "abort");
+    }
+    return hipStreamSynchronize(c->abort_stream) == hipSuccess ? HICR_OK : HICR_EDEVICE;
+  });
 }
 
 }  // extern "C"

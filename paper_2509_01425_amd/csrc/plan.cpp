@@ -90,133 +90,139 @@ extern "C" {
 
 int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched *s,
                      uint32_t flags, hicr_plan *out, uint64_t *bad) {
-  if (!c || !out || (n && !d) || (flags & ~HICR_PLAN_GRAPH)) return HICR_EINVAL;
-  *out = nullptr;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  for (uint64_t i = 0; i < n; i++) {
-    int rc = check_desc(c, d[i]);
-    if (rc != HICR_OK) {
-      if (bad) *bad = i;
-      return fail(c, rc, "plan request %llu rejected", (unsigned long long)i);
-    }
-  }
-  hicr_sched sched = s ? *s : c->def_sched;
-  if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
-    // resolved once: every replay uses the class chosen now
-    int rc = choose_sched(c, d, n, sched.mode, &sched);
-    if (rc != HICR_OK) return rc;
-  } else if (sched.mode != HICR_SCHED_FIXED) {
-    return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
-  }
-  int rc = check_sched(c, sched);
-  if (rc != HICR_OK) return rc;
-
-  hicr_plan p = new (std::nothrow) hicr_plan_s();
-  if (!p) return HICR_ENOMEM;
-  p->c = c;
-  p->n = n;
-  std::vector<hicr_slot> sl;
-  sl.reserve(2 * n);
-  for (uint64_t i = 0; i < n; i++) {
-    sl.push_back(d[i].dst_slot);
-    sl.push_back(d[i].src_slot);
-  }
-  std::sort(sl.begin(), sl.end());
-  sl.erase(std::unique(sl.begin(), sl.end()), sl.end());
-  for (hicr_slot x : sl) c->slots[x].plan_refs++;
-  p->slots = sl;
-
-  std::vector<uint64_t> h(4 * std::max<uint64_t>(n, 1));
-  pack_batch(c, d, n, h.data());
-  DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
-  p->ds = ds;
-  rc = split_batch(c, h.data(), h.data() + 2 * n, n, ds, p->segs);
-  if (rc != HICR_OK) {
-    free_plan(p);
-    return rc;
-  }
-  hipStream_t cs = nullptr;
-  hipError_t e = hipEventCreateWithFlags(&p->ev, hipEventDisableTiming);
-  if (e == hipSuccess && n) e = hipMalloc(&p->d, batch_bytes(n));
-  if (e == hipSuccess && n) e = hipMemcpy(p->d, h.data(), n * 32, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    if (cs) (void)hipStreamDestroy(cs);
-    free_plan(p);
-    return hip_fail(c, e, "allocating a plan");
-  }
-  const uint64_t *dd = static_cast<const uint64_t *>(p->d);
-  uint32_t *tables = n ? batch_tables(p->d, n) : nullptr;
-  // the piece tables are scanned once; every replay reads them
-  rc = launch_scans(c, dd, n, p->segs, ds, tables, cs);
-  if (rc == HICR_OK) {
-    e = hipStreamSynchronize(cs);
-    if (e != hipSuccess) rc = hip_fail(c, e, "scanning a plan");
-  }
-  if (rc != HICR_OK) {
-    (void)hipStreamDestroy(cs);
-    free_plan(p);
-    return rc;
-  }
-  if (flags & HICR_PLAN_GRAPH) {
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) {
-      rc = launch_copies(c, dd, n, p->segs, ds, tables, c->d_counters, cs);
-      hipGraph_t graph = nullptr;
-      hipError_t e2 = hipStreamEndCapture(cs, &graph);
-      p->graph = graph;
-      if (rc == HICR_OK && e2 != hipSuccess) rc = hip_fail(c, e2, "capturing a plan");
-      if (rc == HICR_OK) {
-        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) rc = hip_fail(c, e, "instantiating a plan");
+  return guarded([&]() -> int {
+    if (!c || !out || (n && !d) || (flags & ~HICR_PLAN_GRAPH)) return HICR_EINVAL;
+    *out = nullptr;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    for (uint64_t i = 0; i < n; i++) {
+      int rc = check_desc(c, d[i]);
+      if (rc != HICR_OK) {
+        if (bad) *bad = i;
+        return fail(c, rc, "plan request %llu rejected", (unsigned long long)i);
       }
-    } else {
-      rc = hip_fail(c, e, "capturing a plan");
     }
-  }
-  (void)hipStreamDestroy(cs);
-  if (rc != HICR_OK) {
-    free_plan(p);
-    return rc;
-  }
-  c->plans.push_back(p);
-  *out = p;
-  return HICR_OK;
+    hicr_sched sched = s ? *s : c->def_sched;
+    if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
+      // resolved once: every replay uses the class chosen now
+      int rc = choose_sched(c, d, n, sched.mode, &sched);
+      if (rc != HICR_OK) return rc;
+    } else if (sched.mode != HICR_SCHED_FIXED) {
+      return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
+    }
+    int rc = check_sched(c, sched);
+    if (rc != HICR_OK) return rc;
+
+    hicr_plan p = new (std::nothrow) hicr_plan_s();
+    if (!p) return HICR_ENOMEM;
+    p->c = c;
+    p->n = n;
+    std::vector<hicr_slot> sl;
+    sl.reserve(2 * n);
+    for (uint64_t i = 0; i < n; i++) {
+      sl.push_back(d[i].dst_slot);
+      sl.push_back(d[i].src_slot);
+    }
+    std::sort(sl.begin(), sl.end());
+    sl.erase(std::unique(sl.begin(), sl.end()), sl.end());
+    for (hicr_slot x : sl) c->slots[x].plan_refs++;
+    p->slots = sl;
+
+    std::vector<uint64_t> h(4 * std::max<uint64_t>(n, 1));
+    pack_batch(c, d, n, h.data());
+    DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
+    p->ds = ds;
+    rc = split_batch(c, h.data(), h.data() + 2 * n, n, ds, p->segs);
+    if (rc != HICR_OK) {
+      free_plan(p);
+      return rc;
+    }
+    hipStream_t cs = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&p->ev, hipEventDisableTiming);
+    if (e == hipSuccess && n) e = hipMalloc(&p->d, batch_bytes(n));
+    if (e == hipSuccess && n) e = hipMemcpy(p->d, h.data(), n * 32, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      if (cs) (void)hipStreamDestroy(cs);
+      free_plan(p);
+      return hip_fail(c, e, "allocating a plan");
+    }
+    const uint64_t *dd = static_cast<const uint64_t *>(p->d);
+    uint32_t *tables = n ? batch_tables(p->d, n) : nullptr;
+    // the piece tables are scanned once; every replay reads them
+    rc = launch_scans(c, dd, n, p->segs, ds, tables, cs);
+    if (rc == HICR_OK) {
+      e = hipStreamSynchronize(cs);
+      if (e != hipSuccess) rc = hip_fail(c, e, "scanning a plan");
+    }
+    if (rc != HICR_OK) {
+      (void)hipStreamDestroy(cs);
+      free_plan(p);
+      return rc;
+    }
+    if (flags & HICR_PLAN_GRAPH) {
+      e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+      if (e == hipSuccess) {
+        rc = launch_copies(c, dd, n, p->segs, ds, tables, c->d_counters, cs);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        p->graph = graph;
+        if (rc == HICR_OK && e2 != hipSuccess) rc = hip_fail(c, e2, "capturing a plan");
+        if (rc == HICR_OK) {
+          e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+          if (e != hipSuccess) rc = hip_fail(c, e, "instantiating a plan");
+        }
+      } else {
+        rc = hip_fail(c, e, "capturing a plan");
+      }
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != HICR_OK) {
+      free_plan(p);
+      return rc;
+    }
+    c->plans.push_back(p);
+    *out = p;
+    return HICR_OK;
+  });
 }
 
 int hicr_plan_launch(hicr_plan p, void *stream) {
-  if (!p) return HICR_EINVAL;
-  hicr_ctx c = p->c;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-  hipError_t e = hipSuccess;
-  if (p->launched && s != p->last) e = hipStreamWaitEvent(s, p->ev, 0);
-  if (e == hipSuccess && p->exec) {
-    e = hipGraphLaunch(p->exec, s);
-  } else if (e == hipSuccess && p->n) {
-    const uint64_t *dd = static_cast<const uint64_t *>(p->d);
-    int rc =
-        launch_copies(c, dd, p->n, p->segs, p->ds, batch_tables(p->d, p->n), c->d_counters, s);
-    if (rc != HICR_OK) return rc;
-  }
-  if (e == hipSuccess) e = hipEventRecord(p->ev, s);
-  if (e != hipSuccess) return hip_fail(c, e, "launching a plan");
-  p->launched = true;
-  p->last = s;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!p) return HICR_EINVAL;
+    hicr_ctx c = p->c;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    hipError_t e = hipSuccess;
+    if (p->launched && s != p->last) e = hipStreamWaitEvent(s, p->ev, 0);
+    if (e == hipSuccess && p->exec) {
+      e = hipGraphLaunch(p->exec, s);
+    } else if (e == hipSuccess && p->n) {
+      const uint64_t *dd = static_cast<const uint64_t *>(p->d);
+      int rc =
+          launch_copies(c, dd, p->n, p->segs, p->ds, batch_tables(p->d, p->n), c->d_counters, s);
+      if (rc != HICR_OK) return rc;
+    }
+    if (e == hipSuccess) e = hipEventRecord(p->ev, s);
+    if (e != hipSuccess) return hip_fail(c, e, "launching a plan");
+    p->launched = true;
+    p->last = s;
+    return HICR_OK;
+  });
 }
 
 int hicr_plan_destroy(hicr_plan p) {
-  if (!p) return HICR_EINVAL;
-  hicr_ctx c = p->c;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  int rc = wait_plan(c, p);
-  c->plans.erase(std::remove(c->plans.begin(), c->plans.end(), p), c->plans.end());
-  free_plan(p);
-  return rc;
+  return guarded([&]() -> int {
+    if (!p) return HICR_EINVAL;
+    hicr_ctx c = p->c;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    int rc = wait_plan(c, p);
+    c->plans.erase(std::remove(c->plans.begin(), c->plans.end(), p), c->plans.end());
+    free_plan(p);
+    return rc;
+  });
 }
 
 }  // extern "C"

@@ -447,12 +447,14 @@ int flush_pending(hicr_ctx c) {
 extern "C" {
 
 int hicr_sched_class(uint32_t cls, hicr_sched *out) {
-  if (!out || cls >= HICR_NUM_CLASSES) return HICR_EINVAL;
-  out->chunk_bytes = kChunks[cls / 4];
-  out->wgs_per_desc = kWgs[(cls / 2) % 2];
-  out->unroll = kUnroll[cls % 2];
-  out->mode = HICR_SCHED_FIXED;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!out || cls >= HICR_NUM_CLASSES) return HICR_EINVAL;
+    out->chunk_bytes = kChunks[cls / 4];
+    out->wgs_per_desc = kWgs[(cls / 2) % 2];
+    out->unroll = kUnroll[cls % 2];
+    out->mode = HICR_SCHED_FIXED;
+    return HICR_OK;
+  });
 }
 
 const char *hicr_strerror(int code) {
@@ -473,266 +475,292 @@ const char *hicr_strerror(int code) {
 }
 
 int hicr_last_error(hicr_ctx c, char *buf, size_t n) {
-  if (!c || !buf || n == 0) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  snprintf(buf, n, "%s", c->err.c_str());
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c || !buf || n == 0) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    snprintf(buf, n, "%s", c->err.c_str());
+    return HICR_OK;
+  });
 }
 
 int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
-  if (!out) return HICR_EINVAL;
-  *out = nullptr;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HICR_EINVAL;
-  if (hipSetDevice(device) != hipSuccess) return HICR_EDEVICE;
-  hicr_ctx c = new (std::nothrow) hicr_ctx_s();
-  if (!c) return HICR_ENOMEM;
-  c->device = device;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-    delete c;
-    return HICR_EDEVICE;
-  }
-  c->n_cu = prop.multiProcessorCount;
-  if (copy_occupancy(&c->occ) != 0 || c->occ < 1) c->occ = 1;
-  if (stream) {
-    c->stream = static_cast<hipStream_t>(stream);
-    c->own_stream = false;
-  } else if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-    delete c;
-    return HICR_EDEVICE;
-  } else {
-    c->own_stream = true;
-  }
-  bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipHostMalloc(&c->h_read, 64, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&c->push_ev, hipEventDisableTiming) == hipSuccess;
-  if (ok && (pump_occupancy(&c->pump_occ) != 0 || c->pump_occ < 1)) c->pump_occ = 1;
-  ok = ok && hipStreamCreateWithFlags(&c->up, hipStreamNonBlocking) == hipSuccess;
-  for (int i = 0; ok && i < kNumSubs; i++) {
-    ok = hipEventCreateWithFlags(&c->subs[i].ev, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&c->subs[i].up_ev, hipEventDisableTiming) == hipSuccess;
-  }
-  c->def_sched = hicr_sched{64u << 10, 1, 2, HICR_SCHED_FIXED};
-  if (!ok || alloc_counters(c) != HICR_OK) {
-    hicr_ctx_destroy(c);
-    return HICR_EDEVICE;
-  }
-  *out = c;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!out) return HICR_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HICR_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return HICR_EDEVICE;
+    hicr_ctx c = new (std::nothrow) hicr_ctx_s();
+    if (!c) return HICR_ENOMEM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+      delete c;
+      return HICR_EDEVICE;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    if (copy_occupancy(&c->occ) != 0 || c->occ < 1) c->occ = 1;
+    if (stream) {
+      c->stream = static_cast<hipStream_t>(stream);
+      c->own_stream = false;
+    } else if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return HICR_EDEVICE;
+    } else {
+      c->own_stream = true;
+    }
+    bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipHostMalloc(&c->h_read, 64, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->push_ev, hipEventDisableTiming) == hipSuccess;
+    if (ok && (pump_occupancy(&c->pump_occ) != 0 || c->pump_occ < 1)) c->pump_occ = 1;
+    ok = ok && hipStreamCreateWithFlags(&c->up, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < kNumSubs; i++) {
+      ok = hipEventCreateWithFlags(&c->subs[i].ev, hipEventDisableTiming) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&c->subs[i].up_ev, hipEventDisableTiming) == hipSuccess;
+    }
+    c->def_sched = hicr_sched{64u << 10, 1, 2, HICR_SCHED_FIXED};
+    if (!ok || alloc_counters(c) != HICR_OK) {
+      hicr_ctx_destroy(c);
+      return HICR_EDEVICE;
+    }
+    *out = c;
+    return HICR_OK;
+  });
 }
 
 int hicr_ctx_destroy(hicr_ctx c) {
-  if (!c) return HICR_EINVAL;
-  (void)hipSetDevice(c->device);
-  wait_all(c);
-  destroy_plans(c);
-  destroy_extra(c);
-  destroy_pump_bufs(c);
-  destroy_sched(c);
-  destroy_pool(c);
-  for (Sub &s : c->subs) {
-    if (s.h) (void)hipHostFree(s.h);
-    if (s.d) (void)hipFree(s.d);
-    if (s.ev) (void)hipEventDestroy(s.ev);
-    if (s.up_ev) (void)hipEventDestroy(s.up_ev);
-  }
-  if (c->d_counters) (void)hipFree(c->d_counters);
-  if (c->h_read) (void)hipHostFree(c->h_read);
-  if (c->aux) (void)hipStreamDestroy(c->aux);
-  if (c->up) (void)hipStreamDestroy(c->up);
-  if (c->abort_stream) (void)hipStreamDestroy(c->abort_stream);
-  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
-  delete c;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c) return HICR_EINVAL;
+    (void)hipSetDevice(c->device);
+    wait_all(c);
+    destroy_plans(c);
+    destroy_extra(c);
+    destroy_pump_bufs(c);
+    destroy_sched(c);
+    destroy_pool(c);
+    for (Sub &s : c->subs) {
+      if (s.h) (void)hipHostFree(s.h);
+      if (s.d) (void)hipFree(s.d);
+      if (s.ev) (void)hipEventDestroy(s.ev);
+      if (s.up_ev) (void)hipEventDestroy(s.up_ev);
+    }
+    if (c->d_counters) (void)hipFree(c->d_counters);
+    if (c->h_read) (void)hipHostFree(c->h_read);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
+    if (c->up) (void)hipStreamDestroy(c->up);
+    if (c->abort_stream) (void)hipStreamDestroy(c->abort_stream);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return HICR_OK;
+  });
 }
 
 int hicr_ctx_set_sched(hicr_ctx c, const hicr_sched *s) {
-  if (!c || !s) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (s->mode != HICR_SCHED_FIXED) return fail(c, HICR_EINVAL, "default schedule must be fixed");
-  int rc = check_sched(c, *s);
-  if (rc == HICR_OK) c->def_sched = *s;
-  return rc;
+  return guarded([&]() -> int {
+    if (!c || !s) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (s->mode != HICR_SCHED_FIXED) return fail(c, HICR_EINVAL, "default schedule must be fixed");
+    int rc = check_sched(c, *s);
+    if (rc == HICR_OK) c->def_sched = *s;
+    return rc;
+  });
 }
 
 int hicr_ctx_set_copy_grid(hicr_ctx c, uint32_t wgs_per_cu) {
-  if (!c || wgs_per_cu > 64) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  c->grid_per_cu = (int)wgs_per_cu;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c || wgs_per_cu > 64) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    c->grid_per_cu = (int)wgs_per_cu;
+    return HICR_OK;
+  });
 }
 
 int hicr_ctx_set_pairs(hicr_ctx c, uint32_t pair_mask) {
-  if (!c || (pair_mask & ~HICR_PAIRS_ALL)) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  c->pair_mask = pair_mask;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c || (pair_mask & ~HICR_PAIRS_ALL)) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    c->pair_mask = pair_mask;
+    return HICR_OK;
+  });
 }
 
 int hicr_slot_register(hicr_ctx c, void *ptr, uint64_t size, uint32_t memspace, hicr_slot *out) {
-  if (!c || !out) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  if (!ptr) return fail(c, HICR_EINVAL, "null address");
-  if (size == 0) return fail(c, HICR_EINVAL, "a slot needs a non-zero size");
-  if (memspace != HICR_MEM_HBM && memspace != HICR_MEM_HOST)
-    return fail(c, HICR_EINVAL, "unknown memory space %u", memspace);
-  if (memspace == HICR_MEM_HBM) {
-    hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeDevice ||
-        attr.device != c->device) {
-      (void)hipGetLastError();
-      return fail(c, HICR_EINVAL, "address is not device memory of device %d", c->device);
+  return guarded([&]() -> int {
+    if (!c || !out) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    if (!ptr) return fail(c, HICR_EINVAL, "null address");
+    if (size == 0) return fail(c, HICR_EINVAL, "a slot needs a non-zero size");
+    if (memspace != HICR_MEM_HBM && memspace != HICR_MEM_HOST)
+      return fail(c, HICR_EINVAL, "unknown memory space %u", memspace);
+    if (memspace == HICR_MEM_HBM) {
+      hipPointerAttribute_t attr;
+      if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+          attr.device != c->device) {
+        (void)hipGetLastError();
+        return fail(c, HICR_EINVAL, "address is not device memory of device %d", c->device);
+      }
+      hipDeviceptr_t base = nullptr;
+      size_t alloc = 0;
+      if (hipMemGetAddressRange(&base, &alloc, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, HICR_EINVAL, "address outside every device allocation");
+      }
+      uint64_t b = reinterpret_cast<uint64_t>(base), p = reinterpret_cast<uint64_t>(ptr);
+      if (p - b > alloc || size > alloc - (p - b))
+        return fail(c, HICR_ERANGE, "slot extends past the end of its allocation");
     }
-    hipDeviceptr_t base = nullptr;
-    size_t alloc = 0;
-    if (hipMemGetAddressRange(&base, &alloc, ptr) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(c, HICR_EINVAL, "address outside every device allocation");
+    uint64_t dev_addr = reinterpret_cast<uint64_t>(ptr);
+    if (memspace == HICR_MEM_HOST) {
+      // pinned host memory: the device reaches it at its device-side address
+      hipPointerAttribute_t attr;
+      if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeHost) {
+        (void)hipGetLastError();
+        return fail(c, HICR_EINVAL, "address is not pinned host memory");
+      }
+      void *dp = nullptr;
+      if (hipHostGetDevicePointer(&dp, ptr, 0) != hipSuccess || !dp) {
+        (void)hipGetLastError();
+        return fail(c, HICR_EINVAL, "pinned host memory without a device address");
+      }
+      dev_addr = reinterpret_cast<uint64_t>(dp);
+      void *last = static_cast<char *>(ptr) + (size - 1);
+      void *dlast = nullptr;
+      if (size > 1 && (hipHostGetDevicePointer(&dlast, last, 0) != hipSuccess ||
+                       reinterpret_cast<uint64_t>(dlast) != dev_addr + (size - 1))) {
+        (void)hipGetLastError();
+        return fail(c, HICR_ERANGE, "slot extends past the end of its pinned allocation");
+      }
     }
-    uint64_t b = reinterpret_cast<uint64_t>(base), p = reinterpret_cast<uint64_t>(ptr);
-    if (p - b > alloc || size > alloc - (p - b))
-      return fail(c, HICR_ERANGE, "slot extends past the end of its allocation");
-  }
-  uint64_t dev_addr = reinterpret_cast<uint64_t>(ptr);
-  if (memspace == HICR_MEM_HOST) {
-    // pinned host memory: the device reaches it at its device-side address
-    hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeHost) {
-      (void)hipGetLastError();
-      return fail(c, HICR_EINVAL, "address is not pinned host memory");
-    }
-    void *dp = nullptr;
-    if (hipHostGetDevicePointer(&dp, ptr, 0) != hipSuccess || !dp) {
-      (void)hipGetLastError();
-      return fail(c, HICR_EINVAL, "pinned host memory without a device address");
-    }
-    dev_addr = reinterpret_cast<uint64_t>(dp);
-    void *last = static_cast<char *>(ptr) + (size - 1);
-    void *dlast = nullptr;
-    if (size > 1 && (hipHostGetDevicePointer(&dlast, last, 0) != hipSuccess ||
-                     reinterpret_cast<uint64_t>(dlast) != dev_addr + (size - 1))) {
-      (void)hipGetLastError();
-      return fail(c, HICR_ERANGE, "slot extends past the end of its pinned allocation");
-    }
-  }
-  if (c->slots.size() >= kMaxSlots)
-    return fail(c, HICR_ENOMEM, "at most %u slots per context", kMaxSlots);
-  Slot s;
-  s.base = dev_addr;
-  s.size = size;
-  s.space = memspace;
-  s.live = true;
-  c->slots.push_back(s);
-  *out = (hicr_slot)(c->slots.size() - 1);
-  return HICR_OK;
+    if (c->slots.size() >= kMaxSlots)
+      return fail(c, HICR_ENOMEM, "at most %u slots per context", kMaxSlots);
+    Slot s;
+    s.base = dev_addr;
+    s.size = size;
+    s.space = memspace;
+    s.live = true;
+    c->slots.push_back(s);
+    *out = (hicr_slot)(c->slots.size() - 1);
+    return HICR_OK;
+  });
 }
 
 int hicr_slot_deregister(hicr_ctx c, hicr_slot slot) {
-  if (!c) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
-  for (const hicr_desc &d : c->pending)
-    if (d.dst_slot == slot || d.src_slot == slot)
-      return fail(c, HICR_EBUSY, "slot has unsubmitted transfers; fence first");
-  if (c->slots[slot].plan_refs)
-    return fail(c, HICR_EBUSY, "slot is used by %u plan(s)", c->slots[slot].plan_refs);
-  if (c->slots[slot].dobj_refs)
-    return fail(c, HICR_EBUSY, "slot holds %u published data object(s)", c->slots[slot].dobj_refs);
-  (void)hipSetDevice(c->device);
-  if (any_inflight(c) || extra_inflight(c) || plans_inflight(c))
-    return fail(c, HICR_EBUSY, "transfers in flight; fence first");
-  c->slots[slot].live = false;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
+    for (const hicr_desc &d : c->pending)
+      if (d.dst_slot == slot || d.src_slot == slot)
+        return fail(c, HICR_EBUSY, "slot has unsubmitted transfers; fence first");
+    if (c->slots[slot].plan_refs)
+      return fail(c, HICR_EBUSY, "slot is used by %u plan(s)", c->slots[slot].plan_refs);
+    if (c->slots[slot].dobj_refs)
+      return fail(c, HICR_EBUSY, "slot holds %u published data object(s)", c->slots[slot].dobj_refs);
+    (void)hipSetDevice(c->device);
+    if (any_inflight(c) || extra_inflight(c) || plans_inflight(c))
+      return fail(c, HICR_EBUSY, "transfers in flight; fence first");
+    c->slots[slot].live = false;
+    return HICR_OK;
+  });
 }
 
 int hicr_slot_counters(hicr_ctx c, hicr_slot slot, uint64_t *sent, uint64_t *recv) {
-  if (!c) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
-  (void)hipSetDevice(c->device);
-  hipError_t e = hipMemcpyAsync(c->h_read, c->d_counters + 2 * slot, 16, hipMemcpyDeviceToHost,
-                                c->aux);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->aux);
-  if (e != hipSuccess) return hip_fail(c, e, "reading counters");
-  if (sent) *sent = c->h_read[0];
-  if (recv) *recv = c->h_read[1];
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipMemcpyAsync(c->h_read, c->d_counters + 2 * slot, 16, hipMemcpyDeviceToHost,
+                                  c->aux);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->aux);
+    if (e != hipSuccess) return hip_fail(c, e, "reading counters");
+    if (sent) *sent = c->h_read[0];
+    if (recv) *recv = c->h_read[1];
+    return HICR_OK;
+  });
 }
 
 int hicr_memcpy(hicr_ctx c, hicr_slot dst, uint64_t dst_off, hicr_slot src, uint64_t src_off,
                 uint64_t size) {
-  if (!c) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  hicr_desc d{dst, src, dst_off, src_off, size};
-  int rc = check_desc(c, d);
-  if (rc != HICR_OK) return fail(c, rc, "memcpy rejected");
-  c->pending.push_back(d);
-  if (c->pending.size() >= kMaxLdsDescs) {
-    (void)hipSetDevice(c->device);
-    return flush_pending(c);
-  }
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    hicr_desc d{dst, src, dst_off, src_off, size};
+    int rc = check_desc(c, d);
+    if (rc != HICR_OK) return fail(c, rc, "memcpy rejected");
+    c->pending.push_back(d);
+    if (c->pending.size() >= kMaxLdsDescs) {
+      (void)hipSetDevice(c->device);
+      return flush_pending(c);
+    }
+    return HICR_OK;
+  });
 }
 
 int hicr_memcpy_batch(hicr_ctx c, const hicr_desc *descs, uint64_t n, const hicr_sched *s,
                       void *stream, uint64_t *bad) {
-  if (!c || (n && !descs)) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  hicr_sched sched = s ? *s : c->def_sched;
-  if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
-    int rc = choose_sched(c, descs, n, sched.mode, &sched);
+  return guarded([&]() -> int {
+    if (!c || (n && !descs)) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    hicr_sched sched = s ? *s : c->def_sched;
+    if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
+      int rc = choose_sched(c, descs, n, sched.mode, &sched);
+      if (rc != HICR_OK) return rc;
+    } else if (sched.mode != HICR_SCHED_FIXED) {
+      return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
+    }
+    int rc = check_sched(c, sched);
     if (rc != HICR_OK) return rc;
-  } else if (sched.mode != HICR_SCHED_FIXED) {
-    return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);
-  }
-  int rc = check_sched(c, sched);
-  if (rc != HICR_OK) return rc;
-  rc = flush_pending(c);
-  if (rc != HICR_OK) return rc;
-  return submit(c, descs, n, sched,
-                stream ? static_cast<hipStream_t>(stream) : c->stream, bad, nullptr);
+    rc = flush_pending(c);
+    if (rc != HICR_OK) return rc;
+    return submit(c, descs, n, sched,
+                  stream ? static_cast<hipStream_t>(stream) : c->stream, bad, nullptr);
+  });
 }
 
 int hicr_fence(hicr_ctx c) {
-  if (!c) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  int rc = flush_pending(c);
-  int r2 = wait_all(c);
-  return rc != HICR_OK ? rc : r2;
+  return guarded([&]() -> int {
+    if (!c) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    int rc = flush_pending(c);
+    int r2 = wait_all(c);
+    return rc != HICR_OK ? rc : r2;
+  });
 }
 
 int hicr_fence_slot(hicr_ctx c, hicr_slot slot, uint64_t exp_sent, uint64_t exp_recv,
                     uint64_t timeout_ns) {
-  if (!c) return HICR_EINVAL;
-  {
-    std::lock_guard<std::mutex> g(c->mu);
-    if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
-    (void)hipSetDevice(c->device);
-    int rc = flush_pending(c);
-    if (rc != HICR_OK) return rc;
-  }
-  auto t0 = std::chrono::steady_clock::now();
-  for (;;) {
-    bool busy;
+  return guarded([&]() -> int {
+    if (!c) return HICR_EINVAL;
     {
       std::lock_guard<std::mutex> g(c->mu);
-      busy = any_inflight(c) || extra_inflight(c) || plans_inflight(c);
+      if (slot >= c->slots.size() || !c->slots[slot].live) return fail(c, HICR_EBADSLOT, "bad slot");
+      (void)hipSetDevice(c->device);
+      int rc = flush_pending(c);
+      if (rc != HICR_OK) return rc;
     }
-    uint64_t s = 0, r = 0;
-    int rc = hicr_slot_counters(c, slot, &s, &r);
-    if (rc != HICR_OK) return rc;
-    if (s >= exp_sent && r >= exp_recv) return HICR_OK;
-    if (!busy) return fail(c, HICR_ETIMEDOUT, "expected counts cannot be reached");
-    auto dt = std::chrono::duration_cast<std::chrono::nanoseconds>(
-                  std::chrono::steady_clock::now() - t0).count();
-    if ((uint64_t)dt >= timeout_ns) return fail(c, HICR_ETIMEDOUT, "fence_slot timed out");
-    std::this_thread::sleep_for(std::chrono::microseconds(20));
-  }
+    auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+      bool busy;
+      {
+        std::lock_guard<std::mutex> g(c->mu);
+        busy = any_inflight(c) || extra_inflight(c) || plans_inflight(c);
+      }
+      uint64_t s = 0, r = 0;
+      int rc = hicr_slot_counters(c, slot, &s, &r);
+      if (rc != HICR_OK) return rc;
+      if (s >= exp_sent && r >= exp_recv) return HICR_OK;
+      if (!busy) return fail(c, HICR_ETIMEDOUT, "expected counts cannot be reached");
+      auto dt = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                    std::chrono::steady_clock::now() - t0).count();
+      if ((uint64_t)dt >= timeout_ns) return fail(c, HICR_ETIMEDOUT, "fence_slot timed out");
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+  });
 }
 
 }  // extern "C"

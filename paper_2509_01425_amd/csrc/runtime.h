@@ -186,4 +186,17 @@ int wait_extra(hicr_ctx c);
 bool extra_inflight(hicr_ctx c);
 void destroy_extra(hicr_ctx c);
 
+// Every C entry point runs its body through guarded(): the ABI never throws.
+// The only exceptions host code here can raise come from allocation (a
+// container growing, new, a thread that cannot start), so each becomes
+// HICR_ENOMEM; locks taken in the body are released on the way out.
+template <class F>
+inline int guarded(F &&body) noexcept {
+  try {
+    return body();
+  } catch (...) {
+    return HICR_ENOMEM;
+  }
+}
+
 }  // namespace hicr

@@ -244,197 +244,219 @@ using namespace hicr;
 extern "C" {
 
 int hicr_sched_features(const hicr_desc *descs, uint64_t n, float *out32) {
-  if (!out32 || (n && !descs)) return HICR_EINVAL;
-  if (n == 0) {
-    for (int b = 0; b < kMlpIn; b++) out32[b] = 0.f;
+  return guarded([&]() -> int {
+    if (!out32 || (n && !descs)) return HICR_EINVAL;
+    if (n == 0) {
+      for (int b = 0; b < kMlpIn; b++) out32[b] = 0.f;
+      return HICR_OK;
+    }
+    batch_features(&descs[0].size, n, sizeof(hicr_desc), out32);
     return HICR_OK;
-  }
-  batch_features(&descs[0].size, n, sizeof(hicr_desc), out32);
-  return HICR_OK;
+  });
 }
 
 int hicr_mlp_set_params(hicr_ctx c, const float *params) {
-  if (!c || !params) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  int rc = wait_all(c);
-  if (rc != HICR_OK) return rc;
-  SchedState *s;
-  rc = state(c, &s);
-  if (rc != HICR_OK) return rc;
-  const size_t pb = sizeof(float) * kMlpParams;
-  hipError_t e = hipMemcpy(s->d_params, params, pb, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(s->d_m, 0, pb);
-  if (e == hipSuccess) e = hipMemset(s->d_v, 0, pb);
-  if (e != hipSuccess) return hip_fail(c, e, "loading network parameters");
-  s->step = 0;
-  s->net_loaded = true;
-  s->h_params.assign(params, params + kMlpParams);
-  s->h_t.resize(kMlpParams);
-  net_transpose(s->h_params.data(), s->h_t.data());
-  s->h_stale = false;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c || !params) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    int rc = wait_all(c);
+    if (rc != HICR_OK) return rc;
+    SchedState *s;
+    rc = state(c, &s);
+    if (rc != HICR_OK) return rc;
+    const size_t pb = sizeof(float) * kMlpParams;
+    hipError_t e = hipMemcpy(s->d_params, params, pb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(s->d_m, 0, pb);
+    if (e == hipSuccess) e = hipMemset(s->d_v, 0, pb);
+    if (e != hipSuccess) return hip_fail(c, e, "loading network parameters");
+    s->step = 0;
+    s->net_loaded = true;
+    s->h_params.assign(params, params + kMlpParams);
+    s->h_t.resize(kMlpParams);
+    net_transpose(s->h_params.data(), s->h_t.data());
+    s->h_stale = false;
+    return HICR_OK;
+  });
 }
 
 int hicr_mlp_get_params(hicr_ctx c, float *out) {
-  if (!c || !out) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
-  (void)hipSetDevice(c->device);
-  int rc = wait_all(c);
-  if (rc != HICR_OK) return rc;
-  hipError_t e = hipMemcpy(out, c->sched->d_params, sizeof(float) * kMlpParams,
-                           hipMemcpyDeviceToHost);
-  return e == hipSuccess ? HICR_OK : hip_fail(c, e, "reading network parameters");
+  return guarded([&]() -> int {
+    if (!c || !out) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
+    (void)hipSetDevice(c->device);
+    int rc = wait_all(c);
+    if (rc != HICR_OK) return rc;
+    hipError_t e = hipMemcpy(out, c->sched->d_params, sizeof(float) * kMlpParams,
+                             hipMemcpyDeviceToHost);
+    return e == hipSuccess ? HICR_OK : hip_fail(c, e, "reading network parameters");
+  });
 }
 
 int hicr_mlp_forward(hicr_ctx c, const float *x_dev, uint32_t batch, float *logits_dev) {
-  if (!c || !x_dev || !logits_dev || batch == 0) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
-  (void)hipSetDevice(c->device);
-  SchedState *s = c->sched;
-  int rc = ensure_act(c, s, (int)batch);
-  if (rc != HICR_OK) return rc;
-  hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(logits_dev, s->bufs.z, sizeof(float) * kMlpOut * batch,
-                       hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  return e == hipSuccess ? HICR_OK : hip_fail(c, e, "network forward");
+  return guarded([&]() -> int {
+    if (!c || !x_dev || !logits_dev || batch == 0) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
+    (void)hipSetDevice(c->device);
+    SchedState *s = c->sched;
+    int rc = ensure_act(c, s, (int)batch);
+    if (rc != HICR_OK) return rc;
+    hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(logits_dev, s->bufs.z, sizeof(float) * kMlpOut * batch,
+                         hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? HICR_OK : hip_fail(c, e, "network forward");
+  });
 }
 
 int hicr_mlp_grad(hicr_ctx c, const float *x_dev, const int32_t *y_dev, uint32_t batch,
                   float *grad_dev, float *loss_dev) {
-  if (!c || !x_dev || !y_dev || !grad_dev || batch == 0) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
-  (void)hipSetDevice(c->device);
-  SchedState *s = c->sched;
-  int rc = ensure_act(c, s, (int)batch);
-  if (rc != HICR_OK) return rc;
-  hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
-  if (e == hipSuccess)
-    e = mlp_backward(s->bufs, s->d_params, x_dev, y_dev, (int)batch, grad_dev, loss_dev,
-                     c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  return e == hipSuccess ? HICR_OK : hip_fail(c, e, "network gradient");
+  return guarded([&]() -> int {
+    if (!c || !x_dev || !y_dev || !grad_dev || batch == 0) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
+    (void)hipSetDevice(c->device);
+    SchedState *s = c->sched;
+    int rc = ensure_act(c, s, (int)batch);
+    if (rc != HICR_OK) return rc;
+    hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
+    if (e == hipSuccess)
+      e = mlp_backward(s->bufs, s->d_params, x_dev, y_dev, (int)batch, grad_dev, loss_dev,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? HICR_OK : hip_fail(c, e, "network gradient");
+  });
 }
 
 int hicr_mlp_train_step(hicr_ctx c, const float *x_dev, const int32_t *y_dev, uint32_t batch,
                         float lr, float *loss_dev) {
-  if (!c || !x_dev || !y_dev || batch == 0 || !(lr > 0.f)) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
-  (void)hipSetDevice(c->device);
-  SchedState *s = c->sched;
-  int rc = ensure_act(c, s, (int)batch);
-  if (rc != HICR_OK) return rc;
-  hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
-  if (e == hipSuccess)
-    e = mlp_backward(s->bufs, s->d_params, x_dev, y_dev, (int)batch, s->d_grad, loss_dev,
-                     c->stream);
-  if (e == hipSuccess) e = mlp_adam(s->d_params, s->d_grad, s->d_m, s->d_v, lr, ++s->step, c->stream);
-  if (e == hipSuccess) e = hipEventRecord(c->push_ev, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "network training step");
-  c->push_pending = true;
-  s->h_stale = true;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c || !x_dev || !y_dev || batch == 0 || !(lr > 0.f)) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->sched || !c->sched->net_loaded) return fail(c, HICR_EINVAL, "no network loaded");
+    (void)hipSetDevice(c->device);
+    SchedState *s = c->sched;
+    int rc = ensure_act(c, s, (int)batch);
+    if (rc != HICR_OK) return rc;
+    hipError_t e = mlp_forward(s->bufs, s->d_params, x_dev, (int)batch, c->stream);
+    if (e == hipSuccess)
+      e = mlp_backward(s->bufs, s->d_params, x_dev, y_dev, (int)batch, s->d_grad, loss_dev,
+                       c->stream);
+    if (e == hipSuccess) e = mlp_adam(s->d_params, s->d_grad, s->d_m, s->d_v, lr, ++s->step, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->push_ev, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "network training step");
+    c->push_pending = true;
+    s->h_stale = true;
+    return HICR_OK;
+  });
 }
 
 int hicr_last_choice(hicr_ctx c, uint32_t *cls) {
-  if (!c || !cls) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!c->sched || c->sched->last_cls < 0) return fail(c, HICR_EINVAL, "no learned submission yet");
-  *cls = (uint32_t)c->sched->last_cls;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c || !cls) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->sched || c->sched->last_cls < 0) return fail(c, HICR_EINVAL, "no learned submission yet");
+    *cls = (uint32_t)c->sched->last_cls;
+    return HICR_OK;
+  });
 }
 
 int hicr_tune_add(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t cls) {
-  if (!c || (n && !descs) || cls >= HICR_NUM_CLASSES) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  SchedState *s;
-  int rc = state(c, &s);
-  if (rc != HICR_OK) return rc;
-  std::array<float, kMlpIn> f{};
-  if (n) batch_features(&descs[0].size, n, sizeof(hicr_desc), f.data());
-  s->feats.push_back(f);
-  s->cls.push_back(cls);
-  s->idx_dirty = true;
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c || (n && !descs) || cls >= HICR_NUM_CLASSES) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    SchedState *s;
+    int rc = state(c, &s);
+    if (rc != HICR_OK) return rc;
+    std::array<float, kMlpIn> f{};
+    if (n) batch_features(&descs[0].size, n, sizeof(hicr_desc), f.data());
+    s->feats.push_back(f);
+    s->cls.push_back(cls);
+    s->idx_dirty = true;
+    return HICR_OK;
+  });
 }
 
 int hicr_tune_lookup(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t *cls) {
-  if (!c || (n && !descs) || !cls) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!c->sched || c->sched->feats.empty()) return fail(c, HICR_EINVAL, "empty tuned table");
-  std::array<float, kMlpIn> f{};
-  if (n) batch_features(&descs[0].size, n, sizeof(hicr_desc), f.data());
-  *cls = nearest(c->sched, f.data());
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c || (n && !descs) || !cls) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->sched || c->sched->feats.empty()) return fail(c, HICR_EINVAL, "empty tuned table");
+    std::array<float, kMlpIn> f{};
+    if (n) batch_features(&descs[0].size, n, sizeof(hicr_desc), f.data());
+    *cls = nearest(c->sched, f.data());
+    return HICR_OK;
+  });
 }
 
 int hicr_tune_clear(hicr_ctx c) {
-  if (!c) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (c->sched) {
-    c->sched->feats.clear();
-    c->sched->cls.clear();
-    c->sched->idx_dirty = true;
-  }
-  return HICR_OK;
+  return guarded([&]() -> int {
+    if (!c) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->sched) {
+      c->sched->feats.clear();
+      c->sched->cls.clear();
+      c->sched->idx_dirty = true;
+    }
+    return HICR_OK;
+  });
 }
 
 int hicr_autotune(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t reps, float *times_ms,
                   uint32_t *best) {
-  if (!c || !descs || n == 0 || reps == 0 || reps > 64 || !times_ms) return HICR_EINVAL;
-  std::lock_guard<std::mutex> g(c->mu);
-  (void)hipSetDevice(c->device);
-  int rc = flush_pending(c);
-  if (rc == HICR_OK) rc = wait_all(c);
-  if (rc != HICR_OK) return rc;
-  hipEvent_t t0[64], t1[64];
-  for (uint32_t r = 0; r < reps; r++) {
-    if (hipEventCreate(&t0[r]) != hipSuccess || hipEventCreate(&t1[r]) != hipSuccess)
-      return fail(c, HICR_EDEVICE, "timing events");
-  }
-  uint64_t bad = 0;
-  for (uint32_t k = 0; k < (uint32_t)HICR_NUM_CLASSES && rc == HICR_OK; k++) {
-    hicr_sched sch;
-    hicr_sched_class(k, &sch);
-    SubmitOpts warm;
-    warm.no_count = true;
-    rc = submit(c, descs, n, sch, c->stream, &bad, &warm);
-    std::vector<float> ms(reps);
-    for (uint32_t r = 0; r < reps && rc == HICR_OK; r++) {
-      SubmitOpts o;
-      o.no_count = true;
-      o.t0 = t0[r];
-      o.t1 = t1[r];
-      rc = submit(c, descs, n, sch, c->stream, &bad, &o);
-    }
+  return guarded([&]() -> int {
+    if (!c || !descs || n == 0 || reps == 0 || reps > 64 || !times_ms) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    int rc = flush_pending(c);
     if (rc == HICR_OK) rc = wait_all(c);
-    for (uint32_t r = 0; r < reps && rc == HICR_OK; r++)
-      if (hipEventElapsedTime(&ms[r], t0[r], t1[r]) != hipSuccess)
-        rc = fail(c, HICR_EDEVICE, "reading timing events");
-    if (rc == HICR_OK) {
-      std::sort(ms.begin(), ms.end());
-      times_ms[k] = ms[reps / 2];
+    if (rc != HICR_OK) return rc;
+    hipEvent_t t0[64], t1[64];
+    for (uint32_t r = 0; r < reps; r++) {
+      if (hipEventCreate(&t0[r]) != hipSuccess || hipEventCreate(&t1[r]) != hipSuccess)
+        return fail(c, HICR_EDEVICE, "timing events");
     }
-  }
-  for (uint32_t r = 0; r < reps; r++) {
-    (void)hipEventDestroy(t0[r]);
-    (void)hipEventDestroy(t1[r]);
-  }
-  if (rc != HICR_OK) return rc;
-  if (best) {
-    uint32_t b = 0;
-    for (uint32_t k = 1; k < (uint32_t)HICR_NUM_CLASSES; k++)
-      if (times_ms[k] < times_ms[b]) b = k;  // ties go to the lowest class
-    *best = b;
-  }
-  return HICR_OK;
+    uint64_t bad = 0;
+    for (uint32_t k = 0; k < (uint32_t)HICR_NUM_CLASSES && rc == HICR_OK; k++) {
+      hicr_sched sch;
+      hicr_sched_class(k, &sch);
+      SubmitOpts warm;
+      warm.no_count = true;
+      rc = submit(c, descs, n, sch, c->stream, &bad, &warm);
+      std::vector<float> ms(reps);
+      for (uint32_t r = 0; r < reps && rc == HICR_OK; r++) {
+        SubmitOpts o;
+        o.no_count = true;
+        o.t0 = t0[r];
+        o.t1 = t1[r];
+        rc = submit(c, descs, n, sch, c->stream, &bad, &o);
+      }
+      if (rc == HICR_OK) rc = wait_all(c);
+      for (uint32_t r = 0; r < reps && rc == HICR_OK; r++)
+        if (hipEventElapsedTime(&ms[r], t0[r], t1[r]) != hipSuccess)
+          rc = fail(c, HICR_EDEVICE, "reading timing events");
+      if (rc == HICR_OK) {
+        std::sort(ms.begin(), ms.end());
+        times_ms[k] = ms[reps / 2];
+      }
+    }
+    for (uint32_t r = 0; r < reps; r++) {
+      (void)hipEventDestroy(t0[r]);
+      (void)hipEventDestroy(t1[r]);
+    }
+    if (rc != HICR_OK) return rc;
+    if (best) {
+      uint32_t b = 0;
+      for (uint32_t k = 1; k < (uint32_t)HICR_NUM_CLASSES; k++)
+        if (times_ms[k] < times_ms[b]) b = k;  // ties go to the lowest class
+      *best = b;
+    }
+    return HICR_OK;
+  });
 }
 
 }  // extern "C"
