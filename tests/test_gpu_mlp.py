@@ -44,7 +44,7 @@ def _tensors(torch, x, y):
     return (torch.from_numpy(x).cuda().contiguous(), torch.from_numpy(y).cuda().contiguous())
 
 
-@pytest.mark.parametrize("B", [1, 7, 64, 256, 300])
+@pytest.mark.parametrize("B", [1, 7, 64, 256, 300, 4096])
 def test_forward_and_grad_vs_oracle(env, B):
     torch, H, ctx = env
     theta = he_uniform(B)
