@@ -381,6 +381,29 @@ def test_pump_small_mixed_plan(env, mode):
 
 
 @pytest.mark.parametrize("mode", ["lock", "nolock"])
+def test_pump_odd_ring_sizes(env, mode):
+    """Rings of 8,191 bytes and 5 entries: messages (1..8,191 B) wrap at odd
+    positions, so every wrap split starts and ends off the 16-byte grid."""
+    torch, H, wd, ctx = env
+    from bench import channel_rig
+    seed = 405
+    _say("pump odd rings", mode)
+    plan = wc.plan(n_spsc=5, n_mpsc=2, K=3, total_msgs=900, lo=1, hi=8191, P=8191, E=5,
+                   src_bytes=1 << 16, batch=9)
+    hmode = H.CH_MPSC_LOCK if mode == "lock" else H.CH_MPSC_NOLOCK
+    rig = channel_rig(torch, H, ctx, plan, hmode, seed)
+    trace = torch.zeros(plan.n_msgs, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    rc = H.hicr_channel_pump(ctx, rig["streams"], plan.msg_src_off, plan.msg_size,
+                             trace.data_ptr(), 0, timeout_ns=5 * 10**9)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+    _check_plan(torch, H, rig, plan, seed, mode, trace)
+    for ch in rig["channels"]:
+        assert H.hicr_channel_destroy(ch) == H.OK
+
+
+@pytest.mark.parametrize("mode", ["lock", "nolock"])
 def test_pump_device_tables(env, mode):
     """The small mixed plan with its message tables in device memory
     (HICR_PUMP_DEVICE_TABLES): the same bytes as the oracle, every message
