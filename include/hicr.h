@@ -169,6 +169,23 @@ int hicr_memcpy(hicr_ctx ctx, hicr_slot dst, uint64_t dst_off, hicr_slot src, ui
  * capture: persistent plans (below) are. */
 int hicr_memcpy_batch(hicr_ctx ctx, const hicr_desc *descs, uint64_t n,
                       const hicr_sched *s_or_null, void *stream, uint64_t *bad_index_or_null);
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): hicr_memcpy_batch with the same
+ * arguments, validation, result and counters, that allocates nothing.  The
+ * packed requests and piece tables go to a fixed per-device workspace
+ * (2.5 MiB, held by every device the library runs on until the process
+ * ends), staged through pinned memory the context allocated at creation.
+ *   n > 65,536 requests, a total of 2^38 bytes or more, or a schedule whose
+ *   mode is not HICR_SCHED_FIXED -> HICR_EINVAL, nothing enqueued.
+ * Every call on one device shares the workspace: calls of one context are
+ * ordered (a call on another stream waits for the previous one's launches),
+ * but calls of two contexts on one device that overlap in time race, and
+ * their results are undefined.  Completion and visibility as for
+ * hicr_memcpy_batch (fences).  Pending hicr_memcpy requests stay queued for
+ * the next fence. */
+int hicr_memcpy_batch_noalloc(hicr_ctx ctx, const hicr_desc *descs, uint64_t n,
+                              const hicr_sched *s_or_null, void *stream,
+                              uint64_t *bad_index_or_null);
 /* Sec. 3.1.4 fence: return once every transfer submitted on this context
  * (any stream) has completed and its bytes and counters are visible.
  * HICR_EDEVICE if the device reported an error. */

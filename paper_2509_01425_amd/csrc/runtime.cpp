@@ -23,6 +23,7 @@
 #include "hicr.h"
 #include "chan.h"
 #include "internal.h"
+#include "noalloc.h"
 #include "runtime.h"
 
 using namespace hicr;
@@ -74,6 +75,12 @@ int check_desc(hicr_ctx c, const hicr_desc &d) {
 }
 
 bool any_inflight(hicr_ctx c) {
+  if (c->na_inflight) {
+    if (hipEventQuery(c->na_ev) == hipSuccess)
+      c->na_inflight = false;
+    else
+      return true;
+  }
   for (Sub &s : c->subs) {
     if (!s.inflight) continue;
     if (hipEventQuery(s.ev) == hipSuccess)
@@ -110,6 +117,12 @@ int wait_all(hicr_ctx c) {
   for (Sub &s : c->subs) {
     int r = wait_sub(c, s);
     if (r != HICR_OK) rc = r;
+  }
+  if (c->na_inflight) {
+    hipError_t e = sync_event(c->na_ev);
+    c->na_inflight = false;
+    c->na_up_pending = false;  // the upload precedes the launches on one stream
+    if (e != hipSuccess) rc = hip_fail(c, e, "waiting for a no-allocation batch");
   }
   int r = wait_extra(c);
   if (r != HICR_OK) rc = r;
@@ -520,6 +533,17 @@ int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
       ok = ok && hipEventCreateWithFlags(&c->subs[i].up_ev, hipEventDisableTiming) == hipSuccess;
     }
     c->def_sched = hicr_sched{64u << 10, 1, 2, HICR_SCHED_FIXED};
+    // what hicr_memcpy_batch_noalloc needs, set up once here: the device
+    // workspace's address, pinned staging, its events, and room for its
+    // launch list and error messages (so that no call of it allocates)
+    ok = ok && noalloc_scratch(device, &c->na_scratch) == hipSuccess;
+    ok = ok && hipHostMalloc(&c->na_h, kNoAllocMaxReqs * 32, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->na_up_ev, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->na_ev, hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+      c->segs.reserve(kNoAllocSegCap);
+      c->err.reserve(512);
+    }
     if (!ok || alloc_counters(c) != HICR_OK) {
       hicr_ctx_destroy(c);
       return HICR_EDEVICE;
@@ -547,6 +571,9 @@ int hicr_ctx_destroy(hicr_ctx c) {
     }
     if (c->d_counters) (void)hipFree(c->d_counters);
     if (c->h_read) (void)hipHostFree(c->h_read);
+    if (c->na_h) (void)hipHostFree(c->na_h);
+    if (c->na_up_ev) (void)hipEventDestroy(c->na_up_ev);
+    if (c->na_ev) (void)hipEventDestroy(c->na_ev);
     if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->up) (void)hipStreamDestroy(c->up);
     if (c->abort_stream) (void)hipStreamDestroy(c->abort_stream);
@@ -718,6 +745,65 @@ int hicr_memcpy_batch(hicr_ctx c, const hicr_desc *descs, uint64_t n, const hicr
     if (rc != HICR_OK) return rc;
     return submit(c, descs, n, sched,
                   stream ? static_cast<hipStream_t>(stream) : c->stream, bad, nullptr);
+  });
+}
+
+int hicr_memcpy_batch_noalloc(hicr_ctx c, const hicr_desc *descs, uint64_t n, const hicr_sched *s,
+                              void *stream, uint64_t *bad) {
+  return guarded([&]() -> int {
+    if (!c || (n && !descs)) return HICR_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (n > kNoAllocMaxReqs)
+      return fail(c, HICR_EINVAL, "%llu requests: the no-allocation path takes at most %llu",
+                  (unsigned long long)n, (unsigned long long)kNoAllocMaxReqs);
+    const hicr_sched sched = s ? *s : c->def_sched;
+    if (sched.mode != HICR_SCHED_FIXED)
+      return fail(c, HICR_EINVAL, "the no-allocation path takes a fixed schedule only");
+    int rc = check_sched(c, sched);
+    if (rc != HICR_OK) return rc;
+    if (!c->na_scratch || !c->na_h) return fail(c, HICR_EDEVICE, "no device workspace");
+    if (n == 0) return HICR_OK;
+    (void)hipSetDevice(c->device);
+    // the staging is reused: the previous call's upload must have finished
+    if (c->na_up_pending) {
+      hipError_t e = hipEventSynchronize(c->na_up_ev);
+      if (e != hipSuccess) return hip_fail(c, e, "waiting for the previous upload");
+      c->na_up_pending = false;
+    }
+    uint64_t *h = static_cast<uint64_t *>(c->na_h);
+    int bad_rc = HICR_OK;
+    const uint64_t first_bad = pack_range(c, descs, n, 0, n, h, &bad_rc);
+    if (first_bad < n) {
+      if (bad) *bad = first_bad;
+      return fail(c, bad_rc, "request %llu rejected", (unsigned long long)first_bad);
+    }
+    uint64_t bytes = 0;
+    for (uint64_t i = 0; i < n; i++) bytes += h[2 * n + i];
+    if (bytes >= kNoAllocMaxBytes)
+      return fail(c, HICR_EINVAL, "%llu bytes: the no-allocation path moves less than 2^38 per call",
+                  (unsigned long long)bytes);
+    const DevSched ds{sched.chunk_bytes, sched.wgs_per_desc, sched.unroll, 0};
+    rc = split_batch(c, h, h + 2 * n, n, ds, c->segs);
+    if (rc != HICR_OK) return rc;
+    const hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    // upload, scans, copies and counters all run in order on one stream; a
+    // previous call of this context on another stream must have left the
+    // workspace first
+    hipError_t e = hipSuccess;
+    if (c->na_inflight) e = hipStreamWaitEvent(st, c->na_ev, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->na_scratch, h, n * 32, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(c->na_up_ev, st);
+    if (e != hipSuccess) return hip_fail(c, e, "uploading a batch");
+    c->na_up_pending = true;
+    const uint64_t *dd = static_cast<const uint64_t *>(c->na_scratch);
+    uint32_t *tables = batch_tables(c->na_scratch, n);
+    rc = launch_scans(c, dd, n, c->segs, ds, tables, st);
+    if (rc == HICR_OK) rc = launch_copies(c, dd, n, c->segs, ds, tables, c->d_counters, st);
+    e = hipEventRecord(c->na_ev, st);
+    if (e == hipSuccess) c->na_inflight = true;
+    if (rc != HICR_OK) return rc;
+    if (e != hipSuccess) return hip_fail(c, e, "recording a batch event");
+    return HICR_OK;
   });
 }
 

@@ -100,6 +100,14 @@ struct hicr_ctx_s {
   uint64_t *h_read = nullptr;  // pinned read-back buffer
   hicr::Sub subs[hicr::kNumSubs];
   int next_sub = 0;
+  // hicr_memcpy_batch_noalloc: this device's fixed workspace, pinned staging
+  // allocated with the context, and the events of the last such submission
+  void *na_scratch = nullptr;
+  void *na_h = nullptr;
+  hipEvent_t na_up_ev = nullptr;  // end of its upload (the staging is free again)
+  hipEvent_t na_ev = nullptr;     // end of its last launch
+  bool na_up_pending = false;
+  bool na_inflight = false;
   std::vector<hicr::Seg> segs;  // launches of the submission being queued
   std::vector<hicr_desc> pending;
   hicr_sched def_sched{};

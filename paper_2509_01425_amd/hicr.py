@@ -136,6 +136,8 @@ _SIGNATURES = {
     "hicr_slot_counters": (_int, [_vp, _u32, _pu64, _pu64]),
     "hicr_memcpy": (_int, [_vp, _u32, _u64, _u32, _u64, _u64]),
     "hicr_memcpy_batch": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_sched), _vp, _pu64]),
+    "hicr_memcpy_batch_noalloc": (_int, [_vp, _vp, _u64, ctypes.POINTER(hicr_sched), _vp,
+                                         _pu64]),
     "hicr_fence": (_int, [_vp]),
     "hicr_fence_slot": (_int, [_vp, _u32, _u64, _u64, _u64]),
     "hicr_dobj_publish": (_int, [_vp, _u32, _u64, _u64, _pu64]),
@@ -269,6 +271,15 @@ def hicr_memcpy_batch(ctx, descs: np.ndarray, sched=None, stream: int = 0):
     rc = lib().hicr_memcpy_batch(ctx, d.ctypes.data if d.size else None, d.size,
                                  ctypes.byref(sched) if sched is not None else None,
                                  stream or None, ctypes.byref(bad))
+    return rc, bad.value
+
+
+def hicr_memcpy_batch_noalloc(ctx, descs: np.ndarray, sched=None, stream: int = 0):
+    d = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+    bad = _u64(0)
+    rc = lib().hicr_memcpy_batch_noalloc(ctx, d.ctypes.data if d.size else None, d.size,
+                                         ctypes.byref(sched) if sched is not None else None,
+                                         stream or None, ctypes.byref(bad))
     return rc, bad.value
 
 
