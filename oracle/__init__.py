@@ -77,6 +77,7 @@ def lib():
             "or_vchan_read": (i, [vp, u64, vp]),
             "or_vchan_pop": (i, [vp, u64]),
             "or_vchan_depth": (None, [vp, pu64, pu64]),
+            "or_vchan_replay": (i, [vp, u32, vp, u64, vp, vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -275,3 +276,37 @@ class MPSC:
 
     def ring_for(self, producer: int) -> VChan:
         return self.rings[0] if self.locking else self.rings[producer]
+
+
+def vchan_replay(P: int, E: int, order, blobs, offs, sizes, tagged: bool = False):
+    """Outputs of one ring (P payload bytes, E entries) driven by one
+    sequential schedule in C (``or_vchan_replay``): push t is producer
+    order[t]'s next message (bytes blobs[p][offs[p][k] : + sizes[p][k]]); a
+    push that finds the ring full first consumes the oldest message into the
+    output of the producer its entry names, and the ring is drained at the
+    end.  A producer named more often than it has messages gives EINVAL.
+    Returns (rc, [output bytes of producer p]).  ``tagged`` keeps
+    producer tags (the shared ring of a locking MPSC channel); untagged, every
+    message goes to output 0."""
+    K = len(blobs)
+    ch = VChan(P, E, tagged=tagged)
+    order = np.ascontiguousarray(order, dtype=np.uint32)
+    blobs = [np.ascontiguousarray(b, dtype=np.uint8) for b in blobs]
+    offs = [np.ascontiguousarray(o, dtype=np.uint64) for o in offs]
+    sizes = [np.ascontiguousarray(z, dtype=np.uint64) for z in sizes]
+    for b, o, z in zip(blobs, offs, sizes):
+        if o.size != z.size or (o.size and int((o + z).max()) > b.size):
+            raise ValueError("a message lies outside its producer's source bytes")
+    if tagged:
+        totals = [int(z.sum()) for z in sizes]
+    else:
+        totals = [int(sum(int(z.sum()) for z in sizes))] + [0] * (K - 1)
+    outs = [np.zeros(max(t, 1), dtype=np.uint8) for t in totals]
+    used = np.zeros(K, dtype=np.uint64)
+    counts = np.array([z.size for z in sizes], dtype=np.uint64)
+    arr = ctypes.c_void_p * K
+    rc = lib().or_vchan_replay(
+        ctypes.byref(ch._s), K, _ptr(order), order.size,
+        arr(*[_ptr(b) for b in blobs]), arr(*[_ptr(o) for o in offs]),
+        arr(*[_ptr(z) for z in sizes]), _ptr(counts), arr(*[_ptr(o) for o in outs]), _ptr(used))
+    return rc, [o[:int(u)] for o, u in zip(outs, used)]

@@ -308,3 +308,42 @@ int or_vchan_pop(or_vchan *ch, uint64_t n) {
   ch->hm += n;
   return OR_OK;
 }
+
+/* Consume the oldest message into its producer's output. */
+static int consume_oldest(or_vchan *ch, uint32_t K, unsigned char *const *outs, uint64_t *used) {
+  uint64_t off, size;
+  uint32_t q;
+  int rc = or_vchan_peek(ch, 0, &off, &size, &q);
+  if (rc != OR_OK) return rc;
+  if (q >= K) return OR_EINVAL;
+  rc = or_vchan_read(ch, 0, outs[q] + used[q]);
+  if (rc != OR_OK) return rc;
+  used[q] += size;
+  return or_vchan_pop(ch, 1);
+}
+
+int or_vchan_replay(or_vchan *ch, uint32_t K, const uint32_t *order, uint64_t n,
+                    const unsigned char *const *srcs, const uint64_t *const *offs,
+                    const uint64_t *const *sizes, const uint64_t *counts,
+                    unsigned char *const *outs, uint64_t *used) {
+  uint64_t *next = (uint64_t *)calloc(K ? K : 1, sizeof(uint64_t));
+  if (!next) return OR_ENOMEM;
+  int rc = OR_OK;
+  for (uint64_t t = 0; t < n && rc == OR_OK; t++) {
+    const uint32_t p = order[t];
+    if (p >= K || next[p] >= counts[p]) {
+      rc = OR_EINVAL;
+      break;
+    }
+    const uint64_t k = next[p]++;
+    for (;;) {
+      rc = or_vchan_push(ch, p, srcs[p] + offs[p][k], sizes[p][k]);
+      if (rc != OR_EAGAIN) break;
+      rc = consume_oldest(ch, K, outs, used); /* EAGAIN here: empty yet full */
+      if (rc != OR_OK) break;
+    }
+  }
+  while (rc == OR_OK && ch->tm != ch->hm) rc = consume_oldest(ch, K, outs, used);
+  free(next);
+  return rc;
+}

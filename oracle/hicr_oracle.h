@@ -105,6 +105,21 @@ int or_vchan_read(const or_vchan *ch, uint64_t i, void *dst);
 int or_vchan_pop(or_vchan *ch, uint64_t n);
 void or_vchan_depth(const or_vchan *ch, uint64_t *msgs, uint64_t *bytes);
 
+/* Test harness (no paper passage of its own): drive ring `ch` with one
+ * sequential schedule.  Push number t (t = 0 .. n-1) is made by producer
+ * order[t] (< K) and carries that producer's next message: bytes
+ * srcs[p] + offs[p][k] .. + sizes[p][k], k counting the producer's pushes
+ * (k < counts[p], else OR_EINVAL).
+ * A push that finds no room first consumes the oldest message -- read into
+ * outs[q] at byte used[q], q the producer its entry names (0 untagged), then
+ * popped -- and is retried; at the end the ring is drained the same way.
+ * used[0 .. K) must start at zero.  Returns OR_OK or the first error of a
+ * push, read or pop (OR_EINVAL for a producer id >= K). */
+int or_vchan_replay(or_vchan *ch, uint32_t K, const uint32_t *order, uint64_t n,
+                    const unsigned char *const *srcs, const uint64_t *const *offs,
+                    const uint64_t *const *sizes, const uint64_t *counts,
+                    unsigned char *const *outs, uint64_t *used);
+
 #ifdef __cplusplus
 }
 #endif

@@ -309,3 +309,57 @@ def test_protocol_reservation_catches_unordered_publish_and_no_lock():
     with pytest.raises(protocol.Violation):
         protocol.explore(4, 2, [[2, 1], [1, 2]], locking=True, reserve=True,
                          variant=protocol.Variant(no_lock=True))
+
+
+# ------------------------------------------- whole-ring replay (test harness)
+
+def test_replay_spsc_output_is_the_fifo_concatenation(orc):
+    """or_vchan_replay on one producer: whatever the ring's size, entry
+    count, wraps and back-pressure, the consumer's output is every message in
+    push order (the FIFO definition), byte for byte."""
+    g = np.random.default_rng(31)
+    for case in range(300):
+        P = int(g.integers(1, 65))
+        E = int(g.integers(1, 9))
+        n = int(g.integers(0, 40))
+        blob = g.integers(0, 256, 4096, dtype=np.uint8)
+        sizes = g.integers(0, P + 1, n).astype(np.uint64)
+        offs = np.array([g.integers(0, 4096 - int(z) + 1) for z in sizes], dtype=np.uint64)
+        rc, outs = orc.vchan_replay(P, E, np.zeros(n, np.uint32), [blob], [offs], [sizes])
+        assert rc == orc.OK, case
+        want = np.concatenate([blob[int(o):int(o) + int(z)] for o, z in zip(offs, sizes)]
+                              + [np.zeros(0, np.uint8)])
+        assert np.array_equal(outs[0], want), case
+
+
+def test_replay_tagged_routes_each_producer_in_its_order(orc):
+    """Tagged (locking MPSC) replay of a random merge of three producers'
+    sequences: producer p's output is its own messages in its own order."""
+    g = np.random.default_rng(32)
+    for case in range(100):
+        K, P, E = 3, int(g.integers(8, 65)), int(g.integers(1, 6))
+        blobs = [g.integers(0, 256, 1024, dtype=np.uint8) for _ in range(K)]
+        sizes = [g.integers(0, P + 1, int(g.integers(0, 12))).astype(np.uint64) for _ in range(K)]
+        offs = [np.array([g.integers(0, 1024 - int(z) + 1) for z in zp], dtype=np.uint64)
+                for zp in sizes]
+        order = np.concatenate([np.full(len(z), p, np.uint32) for p, z in enumerate(sizes)])
+        g.shuffle(order)
+        rc, outs = orc.vchan_replay(P, E, order, blobs, offs, sizes, tagged=True)
+        assert rc == orc.OK, case
+        for p in range(K):
+            want = np.concatenate([blobs[p][int(o):int(o) + int(z)]
+                                   for o, z in zip(offs[p], sizes[p])] + [np.zeros(0, np.uint8)])
+            assert np.array_equal(outs[p], want), (case, p)
+
+
+def test_replay_rejects_bad_schedules(orc):
+    blob = np.arange(64, dtype=np.uint8)
+    one = [np.array([0], np.uint64)], [np.array([4], np.uint64)]
+    # a producer named more often than it has messages
+    assert orc.vchan_replay(8, 2, [0, 0], [blob], *one)[0] == orc.EINVAL
+    # an unknown producer
+    assert orc.vchan_replay(8, 2, [1], [blob], *one)[0] == orc.EINVAL
+    # a message larger than the ring
+    assert orc.vchan_replay(3, 2, [0], [blob], *one)[0] == orc.EINVAL
+    with pytest.raises(ValueError):
+        orc.vchan_replay(8, 2, [0], [blob], [np.array([62], np.uint64)], [np.array([4], np.uint64)])
