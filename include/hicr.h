@@ -235,8 +235,10 @@ int hicr_sched_features(const hicr_desc *descs, uint64_t n, float *out32);
 /* Autotuner: run the batch under each of the 12 classes, `reps` timed runs
  * (1..64) after one warm-up, and store the median copy-kernel time of each
  * class in times_ms[12] (and the fastest class, ties to the lowest, in
- * *best_or_null).  The bytes really move (13 * reps times in all), so the
- * batch must be hazard-free; slot counters are not raised.  Synchronous. */
+ * *best_or_null).  The bytes really move (12 * (reps + 1) times in all),
+ * so the batch must be hazard-free: its result is then that of one
+ * application.  Slot counters are not raised.  Synchronous.  descs NULL, n
+ * == 0, reps outside 1..64 or times_ms NULL -> HICR_EINVAL. */
 int hicr_autotune(hicr_ctx ctx, const hicr_desc *descs, uint64_t n, uint32_t reps,
                   float *times_ms, uint32_t *best_or_null);
 /* Tuned table used by HICR_SCHED_TUNED: each entry is an autotuned batch's

@@ -415,10 +415,18 @@ int hicr_autotune(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t reps,
     int rc = flush_pending(c);
     if (rc == HICR_OK) rc = wait_all(c);
     if (rc != HICR_OK) return rc;
-    hipEvent_t t0[64], t1[64];
+    hipEvent_t t0[64] = {}, t1[64] = {};
+    auto destroy_events = [&]() {
+      for (uint32_t r = 0; r < reps; r++) {
+        if (t0[r]) (void)hipEventDestroy(t0[r]);
+        if (t1[r]) (void)hipEventDestroy(t1[r]);
+      }
+    };
     for (uint32_t r = 0; r < reps; r++) {
-      if (hipEventCreate(&t0[r]) != hipSuccess || hipEventCreate(&t1[r]) != hipSuccess)
+      if (hipEventCreate(&t0[r]) != hipSuccess || hipEventCreate(&t1[r]) != hipSuccess) {
+        destroy_events();  // the ones created so far
         return fail(c, HICR_EDEVICE, "timing events");
+      }
     }
     uint64_t bad = 0;
     for (uint32_t k = 0; k < (uint32_t)HICR_NUM_CLASSES && rc == HICR_OK; k++) {
@@ -444,10 +452,7 @@ int hicr_autotune(hicr_ctx c, const hicr_desc *descs, uint64_t n, uint32_t reps,
         times_ms[k] = ms[reps / 2];
       }
     }
-    for (uint32_t r = 0; r < reps; r++) {
-      (void)hipEventDestroy(t0[r]);
-      (void)hipEventDestroy(t1[r]);
-    }
+    destroy_events();
     if (rc != HICR_OK) return rc;
     if (best) {
       uint32_t b = 0;

@@ -4,10 +4,25 @@ Expected values come only from the CPU oracle (``oracle``) applied to inputs
 drawn by ``workloads``; nothing here reads the GPU library's results except
 the arrays handed in for comparison.
 """
+import concurrent.futures as cf
+import os
+
 import numpy as np
 
 import oracle
 from workloads.content import content
+
+
+def workers() -> int:
+    """Host threads for whole-output checks (numpy and the oracle's C code
+    release the interpreter lock); at most 16, the share of one GPU's host."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def pmap(fn, items):
+    """fn over items on a thread pool, results in order."""
+    with cf.ThreadPoolExecutor(max_workers=workers()) as ex:
+        return list(ex.map(fn, items))
 
 
 def abs_ranges(descs, bases):
@@ -103,3 +118,57 @@ def oracle_locking_outputs(P, E, K, order, stream_msgs_by_prod):
         assert ring.pop(1) == oracle.OK
     assert nxt == [len(x) for x in stream_msgs_by_prod], "trace is not a merge of the streams"
     return [np.concatenate(o) if o else np.zeros(0, np.uint8) for o in outs]
+
+
+def stream_blob_msgs(plan, seed, s):
+    """Source bytes of stream s (its whole source slot) and the (offset,
+    size) of each of its messages inside them."""
+    b0, b1 = int(plan.msg_begin[s]), int(plan.msg_begin[s + 1])
+    blob = content(seed, s * plan.src_bytes, plan.src_bytes)
+    return blob, plan.msg_src_off[b0:b1], plan.msg_size[b0:b1]
+
+
+def expected_stream_outputs(plan, seed, mode, trace, streams):
+    """Oracle output of every stream in ``streams`` (stream id -> bytes).
+    A ring with one producer (an SPSC channel, or a non-locking MPSC
+    sub-ring) is replayed through the oracle's ring alone; a locking MPSC
+    channel's shared ring is replayed in the order the device consumed its
+    producers' messages (``trace``: stream id per consumed message, channels
+    in stream order), which must be a merge of their sequences."""
+    per_chan = np.bincount(plan.stream_channel, weights=np.diff(plan.msg_begin),
+                           minlength=plan.n_channels).astype(np.int64)
+    base = np.concatenate([[0], np.cumsum(per_chan)[:-1]])
+    jobs, seen = [], set()
+    for s in streams:
+        c = int(plan.stream_channel[s])
+        if c < plan.n_spsc or mode == "nolock":
+            jobs.append(("one", s))
+        elif c not in seen:
+            seen.add(c)
+            jobs.append(("lock", c))
+
+    def run(job):
+        kind, x = job
+        if kind == "one":
+            blob, o, z = stream_blob_msgs(plan, seed, x)
+            rc, outs = oracle.vchan_replay(plan.P, plan.E, np.zeros(len(z), np.uint32),
+                                           [blob], [o], [z])
+            assert rc == oracle.OK, ("replay", x, rc)
+            return {x: outs[0]}
+        sids = [q for q in range(plan.n_streams) if plan.stream_channel[q] == x]
+        prod_of = {q: int(plan.stream_producer[q]) for q in sids}
+        by_prod = [None] * plan.K
+        for q in sids:
+            by_prod[prod_of[q]] = stream_blob_msgs(plan, seed, q)
+        order = np.array([prod_of[int(q)] for q in trace[base[x]:base[x] + per_chan[x]]],
+                         dtype=np.uint32)
+        rc, outs = oracle.vchan_replay(plan.P, plan.E, order, [b[0] for b in by_prod],
+                                       [b[1] for b in by_prod], [b[2] for b in by_prod],
+                                       tagged=True)
+        assert rc == oracle.OK, ("locking replay: not a merge of the streams", x, rc)
+        return {q: outs[prod_of[q]] for q in sids}
+
+    out = {}
+    for r in pmap(run, jobs):
+        out.update(r)
+    return out
