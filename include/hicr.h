@@ -93,7 +93,11 @@ typedef struct {
  * keeps in flight.  The schedule never changes a byte of the result.
  * mode: HICR_SCHED_FIXED uses the fields as given; HICR_SCHED_TUNED looks the
  * batch up in the context's autotuned table; HICR_SCHED_LEARNED lets the
- * device-resident network pick the class inside the submission. */
+ * schedule network pick the class from the batch's size histogram: for a
+ * submission on the host (the device kernels' arithmetic, from the
+ * parameters last written by the device), for a plan once at creation by
+ * the device forward kernel.  Without a network LEARNED falls back to the
+ * tuned table, then to the context default. */
 #define HICR_SCHED_FIXED 0u
 #define HICR_SCHED_TUNED 1u
 #define HICR_SCHED_LEARNED 2u
@@ -429,10 +433,13 @@ typedef struct {
  * with a single producer (SPSC rings, non-locking MPSC sub-rings) are spread
  * over the remaining workgroups the device holds, balanced by bytes.  Validated on the host (slots, ranges, sizes, one stream per
  * (channel, producer)); HICR_EINVAL if the launch would not fit on the device
- * at once.  Asynchronous; hicr_fence reports a time-out or abort.  A channel
- * has one producer and one consumer per ring: two pump launches that drive
- * the same channel must not overlap (same stream, or ordered by the caller),
- * or the ring's protocol breaks and the pump ends with HICR_ETIMEDOUT. */
+ * at once.  Asynchronous; hicr_fence reports a time-out or abort.  Pumps of
+ * one context never overlap unsafely: a pump queued on another stream than
+ * an unfinished earlier one first waits for it if they share a channel (a
+ * ring has one producer and one consumer), and waits for the oldest others
+ * until all pumps that can run together fit the device at once (every
+ * workgroup of a pump must be resident).  Pumps of two contexts on one
+ * device are not coordinated. */
 int hicr_channel_pump(hicr_ctx ctx, const hicr_stream *streams, uint32_t n_streams,
                       const hicr_pump_io *io, void *stream);
 /* Ask running pumps of this context to stop (they end at their next wait). */

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "chan.h"
+#include "residency.h"
 #include "runtime.h"
 
 using namespace hicr;
@@ -683,7 +684,26 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   a.err = reinterpret_cast<uint32_t *>(d + o_err);
   const uint64_t tns = timeout_ns ? timeout_ns : 10'000'000'000ull;
   a.timeout_ticks = tns / 10;  // 100 MHz device clock
-  hipError_t e = hipMemcpyAsync(d, h, upload, hipMemcpyHostToDevice, s);
+  // Earlier pumps still in flight on other streams: this one follows every
+  // one that drives one of its rings, and the oldest others until all
+  // pumps that can be in flight together fit the device at once.
+  hipError_t e = hipSuccess;
+  {
+    std::vector<LiveLaunch> live;
+    for (const PumpLive &p : c->pump_live) {
+      LiveLaunch l;
+      l.wgs = p.wgs;
+      l.done = hipEventQuery(p.ev) == hipSuccess;
+      l.same_stream = p.stream == s;
+      l.shares_channel = false;
+      for (hicr_channel ch : p.chans)
+        if (chan_idx.count(ch)) l.shares_channel = true;
+      live.push_back(l);
+    }
+    for (size_t i : residency_waits(live, n_wgs, cap))
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, c->pump_live[i].ev, 0);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(d, h, upload, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && team_zero_bytes) e = hipMemsetAsync(d + o_team, 0, team_zero_bytes, s);
   if (e == hipSuccess) e = launch_pump(a, n_wgs, s);
   // error words come back into the (no longer needed) head of the staging
@@ -698,6 +718,14 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   }
   x.abort_word = a.err + 1;
   x.chans = chans;
+  {
+    PumpLive pl;
+    pl.ev = x.ev;
+    pl.stream = s;
+    pl.wgs = n_wgs;
+    pl.chans = chans;
+    c->pump_live.push_back(pl);
+  }
   // the rings' message counters when the next pump starts
   for (uint32_t i = 0; i < n; i++) {
     hicr_channel ch = st[i].channel;
@@ -716,6 +744,11 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
 // and report a device-side error.
 int pump_finish(hicr_ctx c, Extra &x) {
   int rc = HICR_OK;
+  for (size_t i = 0; i < c->pump_live.size(); i++)
+    if (c->pump_live[i].ev == x.ev) {
+      c->pump_live.erase(c->pump_live.begin() + i);
+      break;
+    }
   const uint32_t *err = static_cast<const uint32_t *>(x.h_buf);
   if (err[0] & kErrCorrupt) rc = fail(c, HICR_EDEVICE, "a channel pump read a malformed entry");
   else if (err[0] & kErrTimeout) rc = fail(c, HICR_ETIMEDOUT, "a channel pump made no progress");

@@ -104,8 +104,9 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
     }
     hicr_sched sched = s ? *s : c->def_sched;
     if (sched.mode == HICR_SCHED_TUNED || sched.mode == HICR_SCHED_LEARNED) {
-      // resolved once: every replay uses the class chosen now
-      int rc = choose_sched(c, d, n, sched.mode, &sched);
+      // resolved once, the network's class by the device forward kernel:
+      // every replay uses the class chosen now
+      int rc = choose_sched(c, d, n, sched.mode, &sched, true);
       if (rc != HICR_OK) return rc;
     } else if (sched.mode != HICR_SCHED_FIXED) {
       return fail(c, HICR_EINVAL, "unknown schedule mode %u", sched.mode);

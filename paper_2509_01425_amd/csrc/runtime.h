@@ -69,6 +69,15 @@ struct PumpBuf {
   uint64_t h_cap = 0, d_cap = 0;
 };
 
+// A pump launch whose completion has not been observed yet: what later
+// launches need to stay co-resident with it and off its rings.
+struct PumpLive {
+  hipEvent_t ev = nullptr;
+  hipStream_t stream = nullptr;
+  uint64_t wgs = 0;
+  std::vector<struct ::hicr_channel_s *> chans;
+};
+
 struct Extra {
   hipEvent_t ev = nullptr;
   void *d_buf = nullptr;
@@ -118,6 +127,7 @@ struct hicr_ctx_s {
   uint64_t next_dobj_id = 1;
   std::vector<hicr::Extra> extra;
   std::vector<hicr::PumpBuf> pump_free;  // finished pumps' buffers, for reuse
+  std::vector<hicr::PumpLive> pump_live;  // pumps launched and not yet finished
   int pump_occ = 0;  // pump workgroups per CU
   hipEvent_t push_ev = nullptr;  // last host-API channel push or network step
   bool push_pending = false;
@@ -170,9 +180,12 @@ bool plans_inflight(hicr_ctx c);
 void destroy_plans(hicr_ctx c);
 
 // Schedule selection (sched.cpp): the class for a batch under mode TUNED
-// (nearest tuned-table entry) or LEARNED (the network, evaluated on the host);
-// the context default when neither has data.
-int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out);
+// (nearest tuned-table entry) or LEARNED (the network: on the host, in the
+// device kernels' arithmetic, per submission; by the device forward kernel
+// when on_device, as for a plan's one-time choice); the context default when
+// neither has data.
+int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out,
+                 bool on_device = false);
 void destroy_sched(hicr_ctx c);
 
 // Channel pushes and pumps (channel.cpp).

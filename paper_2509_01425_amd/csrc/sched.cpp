@@ -22,6 +22,7 @@ struct SchedState {
   int step = 0;
   bool net_loaded = false;
   float *d_act = nullptr;  // activations of up to act_cap samples
+  float *d_x = nullptr;    // one feature, for the device inference of a plan's class
   int act_cap = 0;
   MlpBufs bufs{};
   std::vector<std::array<float, kMlpIn>> feats;  // tuned table
@@ -198,8 +199,43 @@ static uint32_t net_class(const float *T, const float *x) {
   return fma ? net_class_fma(T, x) : net_class_axpy(T, x);
 }
 
-int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out) {
+// The network's class for one feature by the device forward kernel (the
+// parameters as they are on the device), read back and argmax-ed with ties to
+// the lowest class.
+static int device_class(hicr_ctx c, SchedState *s, const float *f, uint32_t *cls) {
+  int rc = ensure_act(c, s, 1);
+  if (rc != HICR_OK) return rc;
+  if (!s->d_x && hipMalloc(&s->d_x, sizeof(float) * kMlpIn) != hipSuccess) {
+    s->d_x = nullptr;
+    return fail(c, HICR_ENOMEM, "network input");
+  }
+  static_assert(sizeof(float) * kMlpOut <= 64, "logits fit the read-back buffer");
+  float *z = reinterpret_cast<float *>(c->h_read);
+  hipError_t e = hipMemcpy(s->d_x, f, sizeof(float) * kMlpIn, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = mlp_forward(s->bufs, s->d_params, s->d_x, 1, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(z, s->bufs.z, sizeof(float) * kMlpOut, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "network forward for a plan");
+  uint32_t b = 0;
+  for (uint32_t k = 1; k < (uint32_t)kMlpOut; k++)
+    if (z[k] > z[b]) b = k;
+  *cls = b;
+  return HICR_OK;
+}
+
+int choose_sched(hicr_ctx c, const hicr_desc *d, uint64_t n, uint32_t mode, hicr_sched *out,
+                 bool on_device) {
   SchedState *s = c->sched;
+  if (mode == HICR_SCHED_LEARNED && s && s->net_loaded && on_device) {
+    float f[kMlpIn];
+    batch_features(n ? &d[0].size : nullptr, n, sizeof(hicr_desc), f);
+    uint32_t k = 0;
+    int rc = device_class(c, s, f, &k);
+    if (rc != HICR_OK) return rc;
+    s->last_cls = (int)k;
+    return hicr_sched_class(k, out);
+  }
   if (mode == HICR_SCHED_LEARNED && s && s->net_loaded) {
     if (s->h_stale) {
       // parameters changed by device training steps queued on the context stream
@@ -231,7 +267,7 @@ void destroy_sched(hicr_ctx c) {
   SchedState *s = c->sched;
   if (!s) return;
   for (void *p : {(void *)s->d_params, (void *)s->d_m, (void *)s->d_v, (void *)s->d_grad,
-                  (void *)s->d_loss, (void *)s->d_act})
+                  (void *)s->d_loss, (void *)s->d_act, (void *)s->d_x})
     if (p) (void)hipFree(p);
   delete s;
   c->sched = nullptr;

@@ -362,6 +362,44 @@ def test_pump_small_mixed_plan(env, mode):
         assert H.hicr_channel_destroy(ch) == H.OK
 
 
+def test_pumps_on_two_streams_sharing_channels_run_in_turn(env):
+    """Every stream's messages split in two halves, pumped by two launches on
+    two different streams with no fence between them: the second drives the
+    same rings, so it must wait for the first (a ring has one producer and
+    one consumer).  Each half writes its own output slot, placed so that the
+    two halves of a stream make up its whole output log, which must equal the
+    oracle's."""
+    torch, H, wd, ctx = env
+    from bench import channel_rig
+    seed = 405
+    _say("pump two streams")
+    plan = wc.plan(n_spsc=6, n_mpsc=3, K=3, total_msgs=1500, lo=1, hi=8192, P=8192, E=8,
+                   src_bytes=1 << 16, batch=8)
+    rig = channel_rig(torch, H, ctx, plan, H.CH_MPSC_NOLOCK, seed)
+    out = rig["out"]
+    halves = ([], [])
+    for sid, (ch, p, ss, _os, first, n) in enumerate(rig["streams"]):
+        h = n // 2
+        b1 = int(plan.msg_size[first:first + h].sum())
+        o = int(rig["out_off"][sid])
+        for k, (f, m, base, size) in enumerate(((first, h, o, b1),
+                                                (first + h, n - h, o + b1,
+                                                 int(rig["stream_bytes"][sid]) - b1))):
+            rc, slot = H.hicr_slot_register(ctx, out.data_ptr() + base, max(size, 1))
+            assert rc == H.OK
+            halves[k].append((ch, p, ss, slot, f, m))
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for k, st in enumerate((0, side.cuda_stream)):
+        rc = H.hicr_channel_pump(ctx, halves[k], plan.msg_src_off, plan.msg_size,
+                                 timeout_ns=5 * 10**9, stream=st)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+    assert _check_plan(torch, H, rig, plan, seed, "nolock", None) == plan.n_streams
+    for ch in rig["channels"]:
+        assert H.hicr_channel_destroy(ch) == H.OK
+
+
 @pytest.mark.parametrize("mode", ["lock", "nolock"])
 def test_pump_odd_ring_sizes(env, mode):
     """Rings of 8,191 bytes and 5 entries: messages (1..8,191 B) wrap at odd

@@ -144,6 +144,8 @@ def test_plan_learned_choice_and_rejections(env):
     rc, plan, _ = H.hicr_plan_create(ctx, d, H.make_sched(65536, 1, 2, H.SCHED_LEARNED),
                                      H.PLAN_GRAPH)
     assert rc == H.OK, H.hicr_last_error(ctx)
+    # a plan's class comes from the device forward kernel
+    assert H.hicr_last_choice(ctx) == (H.OK, 9)
     for k in range(2):
         seed = 5200 + k
         wd.fill(pool.data_ptr(), pool_len, seed)
@@ -167,5 +169,39 @@ def test_plan_learned_choice_and_rejections(env):
     assert rc == H.OK
     assert H.hicr_plan_launch(plan) == H.OK
     assert H.hicr_plan_destroy(plan) == H.OK
+    for s in slots:
+        assert H.hicr_slot_deregister(ctx, int(s)) == H.OK
+
+
+def test_plan_device_choice_equals_submission_choice(env):
+    """A plan's class (device forward kernel) and a submission's class (host
+    pass in the same arithmetic) agree on random networks and batches, except
+    where the oracle's two best logits are within 1e-5 (relative)."""
+    torch, H, wd, ctx = env
+    bases, sizes, pool_len, descs, pool, slots, d = _tiny_rig(torch, H, ctx, 3)
+    learned = H.make_sched(65536, 1, 2, H.SCHED_LEARNED)
+    g = np.random.default_rng(12)
+    agree = 0
+    for trial in range(24):
+        theta = he_uniform(300 + trial).astype(np.float32)
+        p = mlp.unpack(theta.astype(np.float64))
+        p["b3"][:] = g.normal(0, 0.5, 12)
+        theta = mlp.pack(p).astype(np.float32)
+        assert H.hicr_mlp_set_params(ctx, theta) == H.OK
+        sub = d[g.permutation(len(d))[:int(g.integers(1, len(d) + 1))]]
+        rc, plan, _ = H.hicr_plan_create(ctx, sub, learned)
+        assert rc == H.OK, H.hicr_last_error(ctx)
+        dev = H.hicr_last_choice(ctx)[1]
+        assert H.hicr_plan_destroy(plan) == H.OK
+        assert H.hicr_memcpy_batch(ctx, sub, learned)[0] == H.OK
+        host = H.hicr_last_choice(ctx)[1]
+        z = mlp.forward(theta.astype(np.float64), mlp.features(sub["size"])[None, :])[0][0]
+        top = np.sort(z)[-2:]
+        if abs(top[1] - top[0]) <= 1e-5 * max(abs(top[1]), 1e-30):
+            continue
+        assert dev == host == int(np.argmax(z)), trial
+        agree += 1
+    assert H.hicr_fence(ctx) == H.OK
+    assert agree >= 20
     for s in slots:
         assert H.hicr_slot_deregister(ctx, int(s)) == H.OK
