@@ -12,7 +12,10 @@ Contents:
                     MPSC channel when producer tags are kept (Sec. 4.3);
   * ``mlp``      -- fp64 reference of the schedule-predicting network;
   * ``protocol`` -- step-level model of the ring protocol with an exhaustive
-                    interleaving explorer.
+                    interleaving explorer;
+  * ``protocol_kernels`` -- the same for the refinements the device kernels
+                    run: batched publication and consumption, the team drain
+                    of a locking ring, ping-pong's striped counters.
 """
 import ctypes
 import os

@@ -1,0 +1,63 @@
+"""Exhaustive interleaving checks of the protocols the device kernels run
+(oracle/protocol_kernels.py; CPU only): batched publication and
+consumption, the team drain of a locking ring, and ping-pong's striped
+counters.  Each accepted configuration is explored completely; each planted
+mistake must be caught."""
+import pytest
+
+from oracle import protocol_kernels as pk
+
+BATCHED = [
+    (4, 4, [2, 1, 3, 2], 2, 1),
+    (4, 3, [2, 1, 3, 2, 1], 2, 2),
+    (5, 4, [1, 2, 3, 1, 2], 3, 2),
+    (4, 4, [1, 3, 1, 2, 1], 2, 1),
+    (6, 3, [2, 3, 1, 4, 2], 2, 2),
+    (3, 3, [3, 0, 2, 1], 3, 1),       # a zero-byte message, a message as large as the ring
+]
+
+
+@pytest.mark.parametrize("cfg", BATCHED)
+def test_batched_ring_accepts(cfg):
+    assert pk.explore_batched(*cfg) > 0
+
+
+@pytest.mark.parametrize("bug", ["publish_before_payload", "release_before_read",
+                                 "batch_room_first_only"])
+@pytest.mark.parametrize("cfg", BATCHED[:5])
+def test_batched_ring_catches(cfg, bug):
+    with pytest.raises(pk.Violation):
+        pk.explore_batched(*cfg, pk.Bug(**{bug: True}))
+
+
+TEAM = [
+    (4, 2, [[1, 2], [2, 1]], 2, 2),
+    (3, 3, [[1, 1], [2, 1]], 2, 1),
+    (5, 3, [[2, 0], [1, 3]], 2, 2),    # a zero-byte message
+    (3, 2, [[1], [1], [2]], 2, 2),     # three producers
+]
+
+
+@pytest.mark.parametrize("cfg", TEAM)
+def test_team_drain_accepts(cfg):
+    assert pk.explore_team(*cfg) > 1000
+
+
+@pytest.mark.parametrize("bug", ["record_after_publish", "no_round_order",
+                                 "start_from_released"])
+@pytest.mark.parametrize("cfg", TEAM)
+def test_team_drain_catches(cfg, bug):
+    with pytest.raises(pk.Violation):
+        pk.explore_team(*cfg, pk.Bug(**{bug: True}))
+
+
+@pytest.mark.parametrize("W,reps", [(2, 2), (3, 2), (2, 3), (4, 1)])
+def test_striped_pingpong_accepts(W, reps):
+    assert pk.explore_striped(W, reps) > 0
+
+
+@pytest.mark.parametrize("bug", ["count_messages", "signal_before_copy"])
+@pytest.mark.parametrize("W,reps", [(2, 2), (3, 2), (4, 1)])
+def test_striped_pingpong_catches(W, reps, bug):
+    with pytest.raises(pk.Violation):
+        pk.explore_striped(W, reps, pk.Bug(**{bug: True}))
