@@ -11,9 +11,14 @@ uses a different seeded batch.
 
 Printed: one JSON line with the whole-job throughput (algorithmic read +
 write bytes / time), per-step p50/p99, the copy kernel's roofline (event-
-timed on the stream it runs on), HBM traffic from committed rocprofv3
-counters when they still match the kernel source, and the CPU oracle's rate
-on a bounded sample of the same workload.
+timed on the stream it runs on) beside the box's reference copy, read and
+write streams, HBM traffic from committed rocprofv3 counters when they still
+match the kernel source; then the channel pumps (both MPSC modes), the
+serving loop (60 s of Poisson arrivals at 2,000 requests/s, 200 GB budget),
+the learned schedule (a 2,000 + 200 batch version of the 20,000 + 1,000
+configuration, which `--workload learned` runs whole), and the CPU oracle's
+rates (one thread and every usable CPU, copy and channel paths) on bounded
+samples of the same workloads.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sched CLASS|tuned|learned]
        python bench.py --calibrate-copy   (plain-copy kernel for counter scaling)
@@ -52,11 +57,43 @@ def traffic_per_launch():
     return t
 
 
+def host_info():
+    """The host the CPU baselines ran on: CPU model, logical CPUs, and the
+    CPUs this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def _greedy_parts(sizes, parts):
+    """Indices of `sizes` split over `parts` workers, longest first onto the
+    least-loaded worker (the partition the all-core baseline uses)."""
+    import heapq
+    heap = [(0, k) for k in range(parts)]
+    out = [[] for _ in range(parts)]
+    for i in np.argsort(-sizes, kind="stable"):
+        load, k = heapq.heappop(heap)
+        out[k].append(int(i))
+        heapq.heappush(heap, (load + int(sizes[i]), k))
+    return [np.array(sorted(o), dtype=np.int64) for o in out if o]
+
+
 def cpu_baseline(batch_descs, target_bytes=12 << 30):
     """Time the CPU oracle on a bounded sample of one batch: requests taken in
     a seeded random order until their sizes reach ``target_bytes``, remapped
     into a host pool (destinations then sources, each request at its original
-    offset modulo 64)."""
+    offset modulo 64).  Timed on one thread, then on every usable CPU with
+    the requests split greedily by bytes (longest first); each thread runs
+    its share through its own oracle context (the oracle's C code runs
+    without the interpreter lock)."""
+    import concurrent.futures as cf
     import oracle
     g = np.random.default_rng(99)
     order = g.permutation(len(batch_descs))
@@ -71,21 +108,110 @@ def cpu_baseline(batch_descs, target_bytes=12 << 30):
     spos = np.concatenate([[0], np.cumsum(sz + 128)[:-1]]) + smod
     src_len = int(spos[-1] + sz[-1] + 64)
     dst = np.zeros(dst_len, np.uint8)
+    dst[:] = 1  # fault every page in before timing
     src = np.ones(src_len, np.uint8)
-    c = oracle.Ctx()
-    _, a = c.register(dst)
-    _, b = c.register(src)
-    d = np.zeros(k, dtype=oracle.DESC_DTYPE)
-    d["dst_slot"], d["src_slot"] = a, b
-    d["dst_off"], d["src_off"], d["size"] = dpos, spos, sz
-    t0 = time.perf_counter()
-    rc, _ = c.memcpy_batch(d)
-    dt = time.perf_counter() - t0
-    assert rc == oracle.OK
     moved = 2 * int(sz.sum())
-    return {"value": round(moved / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} requests ({int(sz.sum())} bytes) of batch 0, single-threaded "
-                      f"byte-loop oracle, {dt:.2f} s"}
+
+    def run_part(idx):
+        c = oracle.Ctx()
+        _, a = c.register(dst)
+        _, b = c.register(src)
+        d = np.zeros(len(idx), dtype=oracle.DESC_DTYPE)
+        d["dst_slot"], d["src_slot"] = a, b
+        d["dst_off"], d["src_off"], d["size"] = dpos[idx], spos[idx], sz[idx]
+        t0 = time.perf_counter()
+        rc, _ = c.memcpy_batch(d)
+        assert rc == oracle.OK
+        return time.perf_counter() - t0
+
+    dt1 = run_part(np.arange(k))
+    threads = len(os.sched_getaffinity(0))
+    parts = _greedy_parts(sz, threads)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        list(ex.map(run_part, parts))
+    dtn = time.perf_counter() - t0
+    return {"value": round(moved / dtn / 1e9, 3), "unit": "GB/s", "cores": len(parts),
+            "kind": "oracle",
+            "sample": f"{k} requests ({int(sz.sum())} bytes) of batch 0 remapped into a host "
+                      f"pool, byte-loop oracle on {len(parts)} threads (greedy byte partition): "
+                      f"{dtn:.2f} s; one thread: {dt1:.2f} s",
+            "single_thread": {"value": round(moved / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1},
+            "host": host_info()}
+
+
+def cpu_channel_baseline(n_streams=32, seed=5):
+    """The oracle's channel path on a sample of the channel configuration: the
+    first n_streams SPSC streams (651 or 652 messages each, 16 B..256 KiB)
+    each replayed through the oracle's 1 MiB / 64-entry ring, on one thread
+    and on every usable CPU (one stream per task).  GB/s counts the same
+    algorithmic bytes as the GPU pump (4 per payload byte + 16 per message)."""
+    import concurrent.futures as cf
+    import oracle
+    from workloads import channels as wc
+    from workloads.content import content
+    plan = wc.plan()
+    work = []
+    for s in range(n_streams):
+        b0, b1 = int(plan.msg_begin[s]), int(plan.msg_begin[s + 1])
+        work.append((content(seed, s * plan.src_bytes, plan.src_bytes),
+                     plan.msg_src_off[b0:b1], plan.msg_size[b0:b1]))
+    payload = int(sum(int(z.sum()) for _, _, z in work))
+    msgs = int(sum(len(z) for _, _, z in work))
+    moved = 4 * payload + 16 * msgs
+
+    def run(w):
+        blob, o, z = w
+        rc, _ = oracle.vchan_replay(plan.P, plan.E, np.zeros(len(z), np.uint32), [blob], [o], [z])
+        assert rc == oracle.OK
+
+    t0 = time.perf_counter()
+    for w in work:
+        run(w)
+    dt1 = time.perf_counter() - t0
+    threads = min(len(os.sched_getaffinity(0)), n_streams)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, work))
+    dtn = time.perf_counter() - t0
+    return {"value": round(moved / dtn / 1e9, 3), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_streams} SPSC streams, {msgs} messages, {payload} payload bytes of "
+                      f"the channel configuration through the oracle's ring: {dtn:.2f} s on "
+                      f"{threads} threads, {dt1:.2f} s on one",
+            "single_thread": {"value": round(moved / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1}}
+
+
+def copy_ceiling(torch, wd, pool, stream, n=4 << 30, reps=3):
+    """What a plain 4 GiB stream reaches on this machine (context for the copy
+    kernel's fraction of peak): the fastest reference copy shape over a grid
+    sweep, the runtime's device-to-device hipMemcpyAsync, and read-only and
+    write-only streams.  GB/s counts read + write bytes (read or write only
+    for the one-sided streams); median of `reps` event-timed launches."""
+    a, b = pool.data_ptr(), pool.data_ptr() + n
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    s = stream.cuda_stream
+
+    def timed(kind, blocks):
+        wd.ref_stream(kind, b, a, n, blocks, sink.data_ptr(), s)  # warm-up
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            wd.ref_stream(kind, b, a, n, blocks, sink.data_ptr(), s)
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    sweep = {bl: 2 * n / (timed(wd.REF_COPY, bl) * 1e-3) / 1e9 for bl in (256, 512, 768, 1024, 2048)}
+    best = max(sweep, key=sweep.get)
+    return {"best_copy_GBps": round(sweep[best], 1), "best_copy_blocks": best,
+            "copy_sweep_GBps": {str(k): round(v, 1) for k, v in sweep.items()},
+            "hipMemcpyAsync_d2d_GBps": round(2 * n / (timed(wd.REF_MEMCPY, 1) * 1e-3) / 1e9, 1),
+            "read_only_GBps": round(n / (timed(wd.REF_READ, 2048) * 1e-3) / 1e9, 1),
+            "write_only_GBps": round(n / (timed(wd.REF_WRITE, 1024) * 1e-3) / 1e9, 1),
+            "bytes": n}
 
 
 def calibrate_copy(n_bytes=4 << 30, reps=3):
@@ -632,6 +758,11 @@ def main():
     ap.add_argument("--learned-train", type=int, default=20000)
     ap.add_argument("--learned-test", type=int, default=1000)
     ap.add_argument("--learned-save", default=None)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--line-learned-train", type=int, default=2000,
+                    help="training batches of the learned-schedule part of the default line")
+    ap.add_argument("--line-learned-test", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -720,26 +851,14 @@ def main():
     per_launch = np.array(moved[args.warmup:], dtype=np.float64)
     achieved = float(np.mean(per_launch / (kern_ms * 1e-3)) / 1e9)
     traffic = traffic_per_launch()
-    # a plain aligned 16-byte copy of 4 GiB inside the same pool, as the
-    # practical ceiling of a read+write stream on this machine (context only)
-    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    cn = 4 << 30
-    wd.ref_copy(pool.data_ptr() + cn, pool.data_ptr(), cn, 1024, stream.cuda_stream)
-    ce_ms = []
-    for _ in range(3):
-        ce0.record(stream)
-        wd.ref_copy(pool.data_ptr() + cn, pool.data_ptr(), cn, 1024, stream.cuda_stream)
-        ce1.record(stream)
-        ce1.synchronize()
-        ce_ms.append(ce0.elapsed_time(ce1))
-    ceiling = 2 * cn / (float(np.median(ce_ms)) * 1e-3) / 1e9
+    ceiling = copy_ceiling(torch, wd, pool, stream)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
             "kernel": "hicr::copy_kernel", "avg_launch_ms": round(float(kern_ms.mean()), 4),
             "algorithmic_bytes_per_launch": int(per_launch.mean()),
-            "plain_copy_ceiling": round(ceiling, 1),
-            "frac_of_plain_copy": round(achieved / ceiling, 4)}
+            "copy_ceiling": ceiling,
+            "frac_of_best_copy": round(achieved / ceiling["best_copy_GBps"], 4)}
     out = {
         "metric": METRIC, "value": round(timed_bytes / total / 1e9, 1), "unit": "GB/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -759,10 +878,29 @@ def main():
     H.hicr_ctx_destroy(ctx)
     del pool
     torch.cuda.empty_cache()
+    def progress(what):
+        print(f"bench: {what} ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+
+    progress("batched copy measured")
     if not args.no_channels:
         out["channels"] = [bench_channels(torch, H, m) for m in (H.CH_MPSC_LOCK, H.CH_MPSC_NOLOCK)]
+        progress("channels measured")
+    if not args.no_serving:
+        sv = bench_serving(torch, H, duration_s=args.serve_seconds, budget=int(args.serve_budget))
+        out["serving"] = {k: sv[k] for k in (
+            "value", "unit", "requests", "duration_s", "rate", "budget_bytes", "latency_p50_ms",
+            "latency_p99_ms", "copy_latency_p99_ms", "burst_latency_p99_ms", "queue_wait_p99_ms",
+            "peak_arena_bytes", "wall_s")}
+        progress("serving measured")
+    if not args.no_learned:
+        ln = bench_learned(torch, H, n_train=args.line_learned_train, n_test=args.line_learned_test)
+        out["learned"] = {k: ln[k] for k in (
+            "n_train", "n_test", "fixed_best_class", "accuracy", "train_seconds",
+            "by_autotune_times", "measured", "wall_seconds")}
+        progress("learned schedule measured")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wm.batched(0))
+        out["cpu_baseline"]["channels"] = cpu_channel_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -89,8 +89,9 @@ typedef struct {
 
 /* Copy schedule.  A batch is cut into pieces of at most chunk_bytes; a
  * request is spread over at least wgs_per_desc pieces (of at least 1 KiB)
- * when it is large enough; unroll is the number of 16-byte vectors each lane
- * keeps in flight.  The schedule never changes a byte of the result.
+ * when it is large enough; unroll sets the depth of the copy loop: a lane
+ * moves rounds of 2 x unroll 16-byte vectors, two rounds in flight.  The
+ * schedule never changes a byte of the result.
  * mode: HICR_SCHED_FIXED uses the fields as given; HICR_SCHED_TUNED looks the
  * batch up in the context's autotuned table; HICR_SCHED_LEARNED lets the
  * schedule network pick the class from the batch's size histogram: for a
@@ -128,8 +129,8 @@ int hicr_last_error(hicr_ctx ctx, char *buf, size_t n);
 int hicr_ctx_set_sched(hicr_ctx ctx, const hicr_sched *s);
 /* Copy workgroups launched per compute unit (the persistent grid is at most
  * CUs x this, capped by what fits).  0 (the default) picks by schedule: 4 for
- * 4 KiB chunks, otherwise 1 at unroll 4 and 2 at unroll 2; at least 4 for a
- * launch of more than 4,096 requests whose average piece is under 16 KiB.  Never changes a byte.
+ * 4 KiB chunks, otherwise 2; at least 4 for a launch of more than 4,096
+ * requests whose average piece is under 16 KiB.  Never changes a byte.
  * wgs_per_cu > 64 -> HICR_EINVAL. */
 int hicr_ctx_set_copy_grid(hicr_ctx ctx, uint32_t wgs_per_cu);
 /* Memory-space pairs memcpy accepts from now on (HICR_PAIR bits; default
@@ -212,7 +213,8 @@ int hicr_fence_slot(hicr_ctx ctx, hicr_slot slot, uint64_t exp_sent, uint64_t ex
  * for replays as for any other transfer.
  *   d[0..n): requests as for hicr_memcpy_batch (copied; the caller may reuse
  *   the array at once).  s_or_null: FIXED, TUNED (resolved now) or LEARNED
- *   (the network runs once now, on the host; every replay uses its choice).  On a rejected request: its code, *bad_index set, no
+ *   (the network's device forward kernel runs once now; every replay uses
+ *   its choice).  On a rejected request: its code, *bad_index set, no
  *   plan.  n = 0 gives a plan whose launches move nothing.
  * While a plan exists the slots it names cannot be deregistered (HICR_EBUSY).
  * Replays of one plan are serialised: a launch on another stream than the

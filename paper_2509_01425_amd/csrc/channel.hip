@@ -47,6 +47,9 @@ __device__ __forceinline__ void st_rel(uint64_t a, uint64_t v) {
   __hip_atomic_store((uint64_t *)a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A 16-byte payload store (ring or output).
+__device__ __forceinline__ void st16(uint64_t a, v4u v) { *(GLOBAL v4u *)a = v; }
+
 // Copy n bytes d <- s with a team of TEAM threads (t = rank in the team):
 // destination-aligned 16-byte stores, source at any alignment, the at most
 // 15 head and 15 tail bytes one by one.  TEAM >= 64.  The code has no
@@ -86,7 +89,7 @@ __device__ __forceinline__ void team_copy(uint64_t d, uint64_t s, uint64_t n, ui
 #pragma unroll
     for (int k = 0; k < U; k++) r[k] = *(const GLOBAL v4u_any *)(s16 + o[k]);
 #pragma unroll
-    for (int k = 0; k < U; k++) *(GLOBAL v4u *)(a0 + o[k]) = r[k];
+    for (int k = 0; k < U; k++) st16(a0 + o[k], r[k]);
   }
   *(GLOBAL unsigned char *)(d + bo) = byte;
 }
@@ -224,7 +227,7 @@ __device__ void seg_copy(const Seg *sg, uint32_t nseg, uint64_t total_v, uint32_
 #pragma unroll
     for (int k = 0; k < U; k++) r[k] = *(const GLOBAL v4u_any *)(sa[k]);
 #pragma unroll
-    for (int k = 0; k < U; k++) *(GLOBAL v4u *)(da[k]) = r[k];
+    for (int k = 0; k < U; k++) st16(da[k], r[k]);
   }
 }
 

@@ -15,12 +15,14 @@
 //      requests).  Against the tiled table, every wavefront takes one
 //      contiguous range of pieces, searches once for its first request (tile,
 //      then request inside the tile) and walks forward request by request;
-//   3. a piece is copied by its wave with 16-byte destination-aligned vector
-//      stores and 16-byte loads at whatever alignment the source has (the HSA
-//      ABI runs gfx950 in unaligned-access mode), `unroll` vectors in flight
-//      per lane, branch-free (see copy_span); the at most 15 bytes before
-//      the first and after the last aligned destination vector are copied
-//      byte by byte, so no store ever touches a byte outside the request;
+//   3. a piece is copied by its wave with buffer loads (at whatever
+//      alignment the source has: gfx950 runs the HSA unaligned-access mode)
+//      and 16-byte destination-aligned buffer stores, both non-temporal;
+//      rounds of 2 x `unroll` 1 KiB rows, the next round's loads issued
+//      before the current round's stores (see copy_span); the at most 15
+//      bytes before the first and after the last aligned destination vector
+//      are copied byte by byte, so no store ever touches a byte outside the
+//      request;
 //   4. completion counting is a separate small kernel (count.hip) queued
 //      behind the copy launches of a submission on the same stream: the
 //      kernel boundary makes every copied byte visible before any counter
@@ -33,17 +35,129 @@
 
 namespace hicr {
 
-typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-typedef v4u v4u_any __attribute__((aligned(1)));  // 16 bytes at any alignment
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
 // Global address space (1): plain global_load/global_store instead of flat.
 #define GLOBAL __attribute__((address_space(1)))
 
-__device__ __forceinline__ v4u load16(uint64_t a) { return *(const GLOBAL v4u_any *)a; }
+// Cache policy of the body's buffer accesses (gfx950 bits: 1 = sc0, 2 = nt,
+// 16 = sc1).  Neither side is touched again by the copy, so the source is
+// read non-temporally and the destination written non-temporally at device
+// scope.
+constexpr int kLoadPolicy = 2;
+constexpr int kStorePolicy = 18;
+// Pieces of at most this many vector bytes take body_small.
+constexpr uint32_t kSmallPiece = 8192;
 
-// Body stores are non-temporal: the destination is not read again by this
-// kernel, and streaming it past the caches measured ~2% faster on gfx950.
-__device__ __forceinline__ void store16(uint64_t a, v4u v) {
-  __builtin_nontemporal_store(v, (GLOBAL v4u *)a);
+// A buffer resource over [base, base + bytes): accesses at or past `bytes`
+// read zero and write nothing (the hardware's range check), which lets the
+// body run whole rounds without clamping its last one.  base and bytes are
+// the same in every lane; base may have any alignment (gfx950 runs the HSA
+// unaligned-access mode).
+__device__ __forceinline__ rsrc_t span_rsrc(uint64_t base, uint32_t bytes) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0,
+                                           (int)__builtin_amdgcn_readfirstlane(bytes),
+                                           0x00020000);
+}
+
+__device__ __forceinline__ v4i bload(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kLoadPolicy);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, v4i v) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kStorePolicy);
+}
+
+// nb bytes (a multiple of 16) from rs to rd in rounds of U vector rows (1 KiB
+// per row), two rounds in flight: round k + 1 is loaded before round k is
+// stored, so a wave never waits for a round's loads with nothing else
+// outstanding.  Offsets past nb read zero and store nothing.
+template <int U>
+__device__ __forceinline__ void body(rsrc_t rs, rsrc_t rd, uint32_t nb, uint32_t lane) {
+  constexpr uint32_t R = 1024u * U;
+  const uint32_t l16 = 16u * lane;
+  v4i a[U], c[U];
+#pragma unroll
+  for (int k = 0; k < U; k++) a[k] = bload(rs, l16 + 1024u * k);
+  for (uint32_t b = 0; b < nb; b += 2 * R) {
+#pragma unroll
+    for (int k = 0; k < U; k++) c[k] = bload(rs, b + R + l16 + 1024u * k);
+#pragma unroll
+    for (int k = 0; k < U; k++) bstore(rd, b + l16 + 1024u * k, a[k]);
+#pragma unroll
+    for (int k = 0; k < U; k++) a[k] = bload(rs, b + 2 * R + l16 + 1024u * k);
+#pragma unroll
+    for (int k = 0; k < U; k++) bstore(rd, b + R + l16 + 1024u * k, c[k]);
+  }
+}
+
+// Small pieces (a halo row, the tail of a request) with plain global
+// accesses: rounds of 4 vector rows, indices past the last vector clamped to
+// it (a repeated vector rewrites equal bytes), stores non-temporal.  On the
+// halo exchange (rows of 5,632 B) the buffer body took 159-168 us per
+// exchange against 154 us for this one.
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef v4u v4u_any __attribute__((aligned(1)));  // 16 bytes at any alignment
+__device__ __forceinline__ void body_small(uint64_t d, uint64_t s, uint32_t nv, uint32_t lane) {
+  for (uint32_t b = 0; b < nv; b += 256) {
+    uint64_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t i = b + lane + 64u * k;
+      o[k] = 16ull * (i < nv ? i : nv - 1);
+    }
+    v4u r[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) r[k] = *(const GLOBAL v4u_any *)(s + o[k]);
+#pragma unroll
+    for (int k = 0; k < 4; k++) __builtin_nontemporal_store(r[k], (GLOBAL v4u *)(d + o[k]));
+  }
+}
+
+// Copy destination bytes [lo, hi) from source address s (the source byte of
+// lo) with one wavefront: the 16-byte destination vectors [a0, a1) by body<U>
+// (loads at the source's own alignment; body_small for at most 8 KiB of
+// vectors), and the at most 15 head bytes
+// [lo, a0) and 15 tail bytes [a1, hi) one by one.  Every lane copies one byte
+// (lanes 0-15 the head bytes, 16-31 the tail bytes, repeating the last one of
+// a range, or byte lo when a range is empty; the other lanes byte lo), so
+// repeated stores write equal values inside the piece; the byte is loaded
+// before the vectors and stored after them, so its latency overlaps theirs.
+// A piece is at most 1 GiB (the chunk limit), so offsets inside it fit 32
+// bits.
+template <int U>
+__device__ __forceinline__ void copy_span(uint64_t lo, uint64_t hi, uint64_t s, uint32_t lane) {
+  uint64_t a0 = (lo + 15) & ~(uint64_t)15;
+  if (a0 > hi) a0 = hi;
+  uint64_t a1 = hi & ~(uint64_t)15;
+  if (a1 < a0) a1 = a0;
+  const uint64_t nh = a0 - lo, nt = hi - a1;
+  uint64_t bo = 0;  // this lane's byte, as an offset from lo
+  if (lane < 16)
+    bo = nh ? (lane < nh ? lane : nh - 1) : 0;
+  else if (lane < 32)
+    bo = nt ? (a1 - lo) + (lane - 16 < nt ? lane - 16 : nt - 1) : 0;
+  // (lo and hi are the same in every lane: a piece without head or tail
+  // bytes, such as an aligned row, skips the byte copy altogether)
+  const bool bytes = (nh | nt) != 0;
+  unsigned char byte = 0;
+  if (bytes) byte = *(const GLOBAL unsigned char *)(s + bo);
+  const uint32_t nb = (uint32_t)(a1 - a0);
+  if (nb > kSmallPiece)
+    body<U>(span_rsrc(s + nh, nb), span_rsrc(a0, nb), nb, lane);
+  else if (nb)
+    body_small(a0, s + nh, nb >> 4, lane);
+  if (bytes) *(GLOBAL unsigned char *)(lo + bo) = byte;
+}
+
+__device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s, uint32_t unroll,
+                                           uint32_t lane) {
+  // rounds of 2 x unroll rows (1 KiB each), two rounds in flight
+  if (unroll >= 4)
+    copy_span<8>(lo, hi, s, lane);
+  else
+    copy_span<4>(lo, hi, s, lane);
 }
 
 // First index i in [0, n) with ends[i] > q (ends strictly increasing, q <
@@ -68,62 +182,6 @@ __device__ __forceinline__ uint32_t find_piece_owner(Ends ends, uint32_t n, uint
   bool gt = (idx >= hi - 1) ? true : (ends[idx] > q);
   uint64_t m = __ballot(gt);
   return lo + (uint32_t)__ffsll((unsigned long long)m) - 1;
-}
-
-// Copy destination bytes [lo, hi) from source address s (the source byte of
-// lo) with one wavefront: 16-byte destination-aligned vectors, `unroll`
-// (U) per lane in flight, and the at most 15 head bytes [lo, a0) and 15 tail
-// bytes [a1, hi) one by one.  The code has no per-lane branch: past the last
-// vector a lane copies the last vector again, and every lane copies one byte
-// (lanes 0-15 the head bytes, 16-31 the tail bytes, repeating the last one
-// of a range, or byte lo when a range is empty; the other lanes byte lo), so
-// repeated stores write equal values inside the piece.  A bounds test per
-// access made the compiler wait for each access of a partial round in turn
-// (four memory latencies for the last round of a piece instead of one); the
-// byte is loaded before the vectors and stored after them, so its latency
-// overlaps theirs.
-template <int U>
-__device__ __forceinline__ void copy_span(uint64_t lo, uint64_t hi, uint64_t s, uint32_t lane) {
-  uint64_t a0 = (lo + 15) & ~(uint64_t)15;
-  if (a0 > hi) a0 = hi;
-  uint64_t a1 = hi & ~(uint64_t)15;
-  if (a1 < a0) a1 = a0;
-  const uint64_t nh = a0 - lo, nt = hi - a1;
-  uint64_t bo = 0;  // this lane's byte, as an offset from lo
-  if (lane < 16)
-    bo = nh ? (lane < nh ? lane : nh - 1) : 0;
-  else if (lane < 32)
-    bo = nt ? (a1 - lo) + (lane - 16 < nt ? lane - 16 : nt - 1) : 0;
-  // (lo and hi are the same in every lane: a piece without head or tail
-  // bytes, such as an aligned row, skips the byte copy altogether)
-  const bool bytes = (nh | nt) != 0;
-  unsigned char byte = 0;
-  if (bytes) byte = *(const GLOBAL unsigned char *)(s + bo);
-  const uint64_t nv = (a1 - a0) >> 4;
-  const uint64_t s16 = s + nh;
-  constexpr uint64_t step = 64ull * U;
-  for (uint64_t base = 0; base < nv; base += step) {
-    uint64_t o[U];
-#pragma unroll
-    for (int k = 0; k < U; k++) {
-      const uint64_t i = base + lane + 64ull * k;
-      o[k] = 16 * (i < nv ? i : nv - 1);
-    }
-    v4u r[U];
-#pragma unroll
-    for (int k = 0; k < U; k++) r[k] = load16(s16 + o[k]);
-#pragma unroll
-    for (int k = 0; k < U; k++) store16(a0 + o[k], r[k]);
-  }
-  if (bytes) *(GLOBAL unsigned char *)(lo + bo) = byte;
-}
-
-__device__ __forceinline__ void copy_range(uint64_t lo, uint64_t hi, uint64_t s, uint32_t unroll,
-                                           uint32_t lane) {
-  if (unroll >= 4)
-    copy_span<4>(lo, hi, s, lane);
-  else
-    copy_span<2>(lo, hi, s, lane);
 }
 
 // Piece j (of length L) of the request dst <- src, size bytes: pieces start

@@ -158,13 +158,13 @@ static int alloc_counters(hicr_ctx c) {
 }
 
 // Copy workgroups per CU when the caller has not fixed it.  Measured on the
-// batched workload (256 CUs): with 64 KiB or 1 MiB pieces one workgroup per CU
-// (four wavefronts) saturates HBM at unroll 4 and two do at unroll 2; more
-// groups only add contention.  4 KiB pieces spend more time per piece on the
-// search and want four.
+// batched workload (256 CUs): with 64 KiB or 1 MiB pieces two workgroups per
+// CU (eight wavefronts, each with two rounds of `unroll` 1 KiB rows in
+// flight) are the fastest at either unroll, 1-2 % above one or four; 4 KiB
+// pieces spend more time per piece on the search and want four.
 int default_grid_per_cu(const DevSched &ds) {
   if (ds.chunk <= (4u << 10)) return 4;
-  return ds.unroll >= 4 ? 1 : 2;
+  return 2;
 }
 
 int split_batch(hicr_ctx c, const uint64_t *hd, const uint64_t *hz, uint64_t n, const DevSched &ds,

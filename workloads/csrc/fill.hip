@@ -3,7 +3,9 @@
 // OOPSLA 2014: state advanced by the golden gamma, variant-13 finaliser) into
 // a device range; the CPU generator in workloads/content.py computes the same
 // stream independently.  wl_ref_copy is a plain aligned 16-byte copy used as
-// the bandwidth reference for counter calibration.
+// the bandwidth reference for counter calibration; wl_ref_stream runs the
+// reference copy, read and write streams that bound what a copy reaches on
+// the box (measurement only).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,6 +46,83 @@ __global__ __launch_bounds__(256) void ref_copy_kernel(uint64_t dst, uint64_t sr
     *(GLOBAL v4u *)(dst + 16 * i) = *(const GLOBAL v4u *)(src + 16 * i);
 }
 
+// Reference streams for the copy ceiling of the box (measurement only).
+// Every wave owns 64 KiB pieces (grid-strided) and moves them with buffer
+// accesses: loads non-temporal, stores non-temporal at device scope, two
+// rounds of 8 KiB in flight -- the fastest plain-copy shape found on gfx950
+// in a sweep of loop shapes, unrolls, grids and cache policies.
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kPiece = 64u << 10, kRound = 8u << 10;
+
+__device__ __forceinline__ rsrc_t piece_rsrc(uint64_t base) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0,
+                                           (int)kPiece, 0x00020000);
+}
+
+__global__ __launch_bounds__(256) void ref_copy_fast_kernel(uint64_t dst, uint64_t src,
+                                                            uint32_t pieces) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  for (uint32_t q = first; q < pieces; q += gridDim.x * 4) {
+    const rsrc_t rs = piece_rsrc(src + (uint64_t)q * kPiece);
+    const rsrc_t rd = piece_rsrc(dst + (uint64_t)q * kPiece);
+    v4i a[8], c[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) a[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * lane + 1024 * k, 0, 2);
+    for (uint32_t b = 0; b < kPiece; b += 2 * kRound) {
+      // b + kRound is inside the piece; the next pair's first round is
+      // clamped to this one at the piece's end
+      const uint32_t nb = b + 2 * kRound < kPiece ? b + 2 * kRound : b;
+#pragma unroll
+      for (int k = 0; k < 8; k++)
+        c[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, b + kRound + 16 * lane + 1024 * k, 0, 2);
+#pragma unroll
+      for (int k = 0; k < 8; k++)
+        __builtin_amdgcn_raw_buffer_store_b128(a[k], rd, b + 16 * lane + 1024 * k, 0, 18);
+#pragma unroll
+      for (int k = 0; k < 8; k++)
+        a[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, nb + 16 * lane + 1024 * k, 0, 2);
+#pragma unroll
+      for (int k = 0; k < 8; k++)
+        __builtin_amdgcn_raw_buffer_store_b128(c[k], rd, b + kRound + 16 * lane + 1024 * k, 0, 18);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void ref_read_kernel(uint64_t src, uint32_t pieces,
+                                                       uint32_t *sink) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  v4i acc = {0, 0, 0, 0};
+  for (uint32_t q = first; q < pieces; q += gridDim.x * 4) {
+    const rsrc_t rs = piece_rsrc(src + (uint64_t)q * kPiece);
+    for (uint32_t b = 0; b < kPiece; b += 4096) {
+      v4i r[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) r[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, b + 16 * lane + 1024 * k, 0, 2);
+#pragma unroll
+      for (int k = 0; k < 4; k++) acc ^= r[k];
+    }
+  }
+  if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x5EED5EED) sink[0] = 1;  // keeps the loads
+}
+
+__global__ __launch_bounds__(256) void ref_write_kernel(uint64_t dst, uint32_t pieces) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const v4i v = {1, 2, 3, (int)lane};
+  for (uint32_t q = first; q < pieces; q += gridDim.x * 4) {
+    const rsrc_t rd = piece_rsrc(dst + (uint64_t)q * kPiece);
+    for (uint32_t b = 0; b < kPiece; b += 4096) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) __builtin_amdgcn_raw_buffer_store_b128(v, rd, b + 16 * lane + 1024 * k, 0, 18);
+    }
+  }
+}
+
 static uint64_t host_sm64(uint64_t seed, uint64_t k) {
   uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -78,6 +157,31 @@ int wl_ref_copy(void *dst, const void *src, uint64_t n_bytes, uint32_t blocks, v
   if (((uint64_t)dst & 15) || ((uint64_t)src & 15) || (n_bytes & 15) || blocks == 0) return -1;
   hipLaunchKernelGGL(ref_copy_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                      (uint64_t)dst, (uint64_t)src, n_bytes / 16);
+  return hipGetLastError() == hipSuccess ? 0 : -9;
+}
+
+// Reference streams of n_bytes (a multiple of 64 KiB, both pointers 16-byte
+// aligned): kind 0 = copy src -> dst, 1 = read src, 2 = write dst, 3 = the
+// runtime's device-to-device hipMemcpyAsync.  sink: 4 device bytes for kind 1.
+int wl_ref_stream(int kind, void *dst, const void *src, uint64_t n_bytes, uint32_t blocks,
+                  void *sink, void *stream) {
+  if (((uint64_t)dst & 15) || ((uint64_t)src & 15) || (n_bytes % kPiece) || blocks == 0 ||
+      n_bytes / kPiece > 0xFFFFFFFFull)
+    return -1;
+  const uint32_t pieces = (uint32_t)(n_bytes / kPiece);
+  hipStream_t s = (hipStream_t)stream;
+  if (kind == 0)
+    hipLaunchKernelGGL(ref_copy_fast_kernel, dim3(blocks), dim3(256), 0, s, (uint64_t)dst,
+                       (uint64_t)src, pieces);
+  else if (kind == 1 && sink)
+    hipLaunchKernelGGL(ref_read_kernel, dim3(blocks), dim3(256), 0, s, (uint64_t)src, pieces,
+                       (uint32_t *)sink);
+  else if (kind == 2)
+    hipLaunchKernelGGL(ref_write_kernel, dim3(blocks), dim3(256), 0, s, (uint64_t)dst, pieces);
+  else if (kind == 3)
+    return hipMemcpyAsync(dst, src, n_bytes, hipMemcpyDeviceToDevice, s) == hipSuccess ? 0 : -9;
+  else
+    return -1;
   return hipGetLastError() == hipSuccess ? 0 : -9;
 }
 

@@ -38,6 +38,10 @@ def lib():
         L.wl_ref_copy.restype = ctypes.c_int
         L.wl_ref_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                   ctypes.c_uint32, ctypes.c_void_p]
+        L.wl_ref_stream.restype = ctypes.c_int
+        L.wl_ref_stream.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                    ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -52,6 +56,19 @@ def ref_copy(dst: int, src: int, n_bytes: int, blocks: int = 4096, stream: int =
     rc = lib().wl_ref_copy(dst, src, n_bytes, blocks, stream or None)
     if rc != 0:
         raise RuntimeError(f"wl_ref_copy failed ({rc})")
+
+
+REF_COPY, REF_READ, REF_WRITE, REF_MEMCPY = 0, 1, 2, 3
+
+
+def ref_stream(kind: int, dst: int, src: int, n_bytes: int, blocks: int = 1024, sink: int = 0,
+               stream: int = 0) -> None:
+    """Reference HBM streams (measurement only): copy, read, write, or the
+    runtime's device-to-device memcpy of n_bytes (a multiple of 64 KiB)."""
+    rc = lib().wl_ref_stream(kind, dst or None, src or None, n_bytes, blocks, sink or None,
+                             stream or None)
+    if rc != 0:
+        raise RuntimeError(f"wl_ref_stream failed ({rc})")
 
 
 if __name__ == "__main__":
