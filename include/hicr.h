@@ -90,7 +90,7 @@ typedef struct {
 /* Copy schedule.  A batch is cut into pieces of at most chunk_bytes; a
  * request is spread over at least wgs_per_desc pieces (of at least 1 KiB)
  * when it is large enough; unroll sets the depth of the copy loop: a lane
- * moves rounds of 2 x unroll 16-byte vectors, two rounds in flight.  The
+ * moves rounds of 4 x unroll 16-byte vectors, two rounds in flight.  The
  * schedule never changes a byte of the result.
  * mode: HICR_SCHED_FIXED uses the fields as given; HICR_SCHED_TUNED looks the
  * batch up in the context's autotuned table; HICR_SCHED_LEARNED lets the
