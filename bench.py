@@ -22,7 +22,7 @@ samples of the same workloads.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sched CLASS|tuned|learned]
        python bench.py --calibrate-copy   (plain-copy kernel for counter scaling)
-       python bench.py --workload {channels,learned,serving,pingpong,tiny,halo,memspace}
+       python bench.py --workload {channels,learned,serving,pingpong,tiny,halo,memspace,placement}
 """
 import argparse
 import hashlib
@@ -739,6 +739,66 @@ def bench_halo(torch, H, N=704, Py=2, Pz=22, h=2, iters=200, reps=3):
     return out
 
 
+def bench_placement(torch, H, allocations=8, batches=2, reps=3, shifts=(0, 4096, (256 << 20) + 4096)):
+    """The batched workload's rate against the pool's physical placement:
+    the pool is allocated, filled and freed `allocations` times in one
+    process (the caching allocator hands back the same virtual range; the
+    driver places the physical pages anew), and each allocation runs the
+    batched workload (class 5, library default grid) with the slot layout at
+    a few shifts inside it.  The headline line uses one ordinary allocation;
+    this mode only reports how much the placement moves the same kernel."""
+    from workloads import device as wd
+    from workloads import memcpy as wm
+    stream = torch.cuda.Stream()
+    rc, ctx = H.hicr_ctx_create(0, stream.cuda_stream)
+    assert rc == H.OK, H.hicr_strerror(rc)
+    sched = parse_sched(H, "5")
+    descs = [wm.batched(b) for b in range(batches)]
+    span = max(shifts)
+    out = []
+    for a in range(allocations):
+        pool = torch.empty(wm.B_POOL + span, dtype=torch.uint8, device="cuda")
+        wd.fill(pool.data_ptr(), wm.B_POOL + span, 7, 0, stream.cuda_stream)
+        torch.cuda.synchronize()
+        by_shift = {}
+        for sh in shifts:
+            bases, sizes = wm.batched_slots()
+            slots = np.empty(len(bases), dtype=np.uint32)
+            for k, (b, z) in enumerate(zip(bases, sizes)):
+                rc, slots[k] = H.hicr_slot_register(ctx, pool.data_ptr() + sh + int(b), int(z),
+                                                    H.MEM_HBM)
+                assert rc == H.OK
+            rates = []
+            for d0 in descs:
+                d = d0.copy()
+                d["dst_slot"] = slots[d["dst_slot"]]
+                d["src_slot"] = slots[d["src_slot"]]
+                rc, _ = H.hicr_memcpy_batch(ctx, d, sched)
+                assert rc == H.OK and H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+                ms = []
+                for _ in range(reps):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    rc, _ = H.hicr_memcpy_batch(ctx, d, sched)
+                    e1.record(stream)
+                    assert rc == H.OK and H.hicr_fence(ctx) == H.OK
+                    e1.synchronize()
+                    ms.append(e0.elapsed_time(e1))
+                rates.append(round(2 * int(d["size"].sum()) / (np.median(ms) * 1e-3) / 1e9, 1))
+            for k in slots:
+                assert H.hicr_slot_deregister(ctx, int(k)) == H.OK
+            by_shift[str(sh)] = rates
+        out.append({"allocation": a, "virtual_base": hex(pool.data_ptr()), "GBps_by_layout_shift": by_shift})
+        print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+        del pool
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    H.hicr_ctx_destroy(ctx)
+    return {"workload": "batched slot memcpy, class 5, one pool allocated and freed per row",
+            "allocations": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -752,7 +812,7 @@ def main():
                     help="copy workgroups per CU (0: the library's per-class default)")
     ap.add_argument("--workload", default="batched",
                     choices=["batched", "channels", "learned", "serving", "pingpong", "tiny",
-                             "halo", "memspace"])
+                             "halo", "memspace", "placement"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-budget", type=float, default=200e9)
     ap.add_argument("--learned-train", type=int, default=20000)
@@ -784,6 +844,9 @@ def main():
         return
     if args.workload == "halo":
         print(json.dumps({"halo": bench_halo(torch, H)}), flush=True)
+        return
+    if args.workload == "placement":
+        print(json.dumps({"placement": bench_placement(torch, H)}), flush=True)
         return
     if args.workload == "tiny":
         print(json.dumps({"tiny": bench_tiny(torch, H)}), flush=True)
