@@ -11,7 +11,12 @@ scope, which give the same orders):
 * ``explore_batched`` -- one producer publishes up to B messages with one
   counter store, after taking every leading message that fits the room it
   saw; one consumer takes up to C published messages at once and releases
-  their room with two stores (bytes, then entries).
+  their room with two stores (bytes, then entries).  With S > 1 a full
+  sub-batch of B messages may wait for up to S - 1 more before one store
+  publishes them all (whether it waits is left open: both choices are
+  explored, so every rule the kernel may use to decide is covered), and a
+  producer that finds no room for its next message publishes what it holds
+  first (the consumer cannot free room for messages it has not seen).
 * ``explore_team`` -- a locking MPSC ring (ticket lock held only to check
   room and reserve entries and bytes) drained by a team of consumers: a
   member claims the next round number, defines the round once the previous
@@ -47,6 +52,7 @@ class Bug:
     start_from_released: bool = False      # team: a round starts at the released counter
     count_messages: bool = False           # striped: counters waited on per message, not stripe
     signal_before_copy: bool = False       # striped: a stripe counted before it is copied
+    no_publish_when_blocked: bool = False  # batched, S > 1: blocked with unpublished messages
 
 
 def _dfs(start, succ, done, max_states):
@@ -74,29 +80,33 @@ def _set(t, i, v):
 
 # ------------------------------------------------------------ batched ring
 
-def explore_batched(P, E, sizes, B, C, bug=Bug(), max_states=3_000_000):
+def explore_batched(P, E, sizes, B, C, bug=Bug(), max_states=3_000_000, S=1):
     """One producer stream of messages ``sizes`` through one ring of P bytes
-    and E entries; producer batches of at most B messages, consumer batches
-    of at most C.  Returns the number of states visited."""
+    and E entries; producer sub-batches of at most B messages, up to S of
+    them per publication; consumer batches of at most C.  Returns the number
+    of states visited."""
     n = len(sizes)
     offs = [sum(sizes[:i]) for i in range(n)]  # stream byte offset of message i
 
     # shared: cells (P markers), ents (E), tm (published), hm, hb (released)
-    # producer: (m, phase, j, my_tm, my_tb, hm_seen, cur msg, cur byte)
+    # producer: (m, phase, j, my_tm, my_tb, hm_seen, cur msg, cur byte, pend)
+    #   (my_tm, my_tb count the messages copied, published or not; pend is
+    #   the number of full sub-batches copied and not yet published)
     # consumer: (phase, hm_loc, hb_loc, k, cur msg, cur byte)
     # rset: frozenset of markers read
     start = (tuple([None] * P), tuple([None] * E), 0, 0, 0,
-             (0, "rd_hm", 0, 0, 0, 0, 0, 0), ("poll", 0, 0, 0, 0, 0), frozenset(), 0)
+             (0, "rd_hm", 0, 0, 0, 0, 0, 0, 0), ("poll", 0, 0, 0, 0, 0), frozenset(), 0)
 
     def succ(st):
         cells, ents, tm, hm, hb, pr, co, rset, ndone = st
-        m, ph, j, my_tm, my_tb, hm_seen, cm, cb = pr
+        m, ph, j, my_tm, my_tb, hm_seen, cm, cb, pend = pr
 
         def P_(**kw):
-            v = dict(m=m, ph=ph, j=j, my_tm=my_tm, my_tb=my_tb, hm_seen=hm_seen, cm=cm, cb=cb)
+            v = dict(m=m, ph=ph, j=j, my_tm=my_tm, my_tb=my_tb, hm_seen=hm_seen, cm=cm, cb=cb,
+                     pend=pend)
             v.update(kw)
             return (v["m"], v["ph"], v["j"], v["my_tm"], v["my_tb"], v["hm_seen"], v["cm"],
-                    v["cb"])
+                    v["cb"], v["pend"])
 
         # ---- producer
         if m < n:
@@ -117,6 +127,9 @@ def explore_batched(P, E, sizes, B, C, bug=Bug(), max_states=3_000_000):
                 if take:
                     nxt = "pub_early" if bug.publish_before_payload else "ents"
                     yield (cells, ents, tm, hm, hb, P_(ph=nxt, j=take), co, rset, ndone)
+                elif pend and not bug.no_publish_when_blocked:
+                    # no room: publish what is held, then look again
+                    yield (cells, ents, my_tm, hm, hb, P_(ph="rd_hm", pend=0), co, rset, ndone)
                 elif hm != hm_seen:
                     # the room seen was stale: look again
                     yield (cells, ents, tm, hm, hb, P_(ph="rd_hm"), co, rset, ndone)
@@ -141,9 +154,15 @@ def explore_batched(P, E, sizes, B, C, bug=Bug(), max_states=3_000_000):
                     yield (nc, ents, tm, hm, hb, P_(cm=cm, cb=cb + 1), co, rset, ndone)
                 else:
                     nb = my_tb + offs[m + j - 1] + sizes[m + j - 1] - offs[m]
+                    if ph == "pay" and j == B and pend + 1 < S and m + j < n:
+                        # a full sub-batch, more to come: it may be held for the next one
+                        yield (cells, ents, tm, hm, hb,
+                               P_(m=m + j, ph="rd_hm", my_tm=my_tm + j, my_tb=nb, pend=pend + 1),
+                               co, rset, ndone)
                     if ph == "pay":
                         yield (cells, ents, my_tm + j, hm, hb,
-                               P_(m=m + j, ph="rd_hm", my_tm=my_tm + j, my_tb=nb), co, rset, ndone)
+                               P_(m=m + j, ph="rd_hm", my_tm=my_tm + j, my_tb=nb, pend=0), co,
+                               rset, ndone)
                     else:
                         yield (cells, ents, tm, hm, hb,
                                P_(m=m + j, ph="rd_hm", my_tm=my_tm + j, my_tb=nb), co, rset, ndone)

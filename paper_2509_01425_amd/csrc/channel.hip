@@ -18,10 +18,13 @@
 // producer waves (one stream each) or one consumer (all four waves).  Waits
 // poll with relaxed device-scope loads and take one acquire fence once the
 // condition holds (an acquire per poll would invalidate the L2 on every
-// spin).  Producers publish up to 16 messages per release (8 on a locking
-// ring) and copy a batch message by message; consumers take up to 32 per
-// release across all of their rings and copy each batch as one index space
-// of 16-byte vectors.  Producers check every message against their stream's
+// spin).  Producers copy up to 16 messages at a time (8 on a locking ring),
+// message by message; the producer of a long stream through a ring of its
+// own holds full batches of 16 unpublished, up to a ring's worth of entries
+// (E / 16 batches), and publishes them with one release (fewer releases, each
+// of which writes back the XCD's L2); consumers take up to 32 per release
+// across all of their rings and copy each batch as one index space of
+// 16-byte vectors.  Producers check every message against their stream's
 // slots before moving a byte.  The host launches no more workgroups than the
 // device holds at once, and every wait gives up after a no-progress time-out
 // or on the abort word, so every wave exits.
@@ -242,7 +245,19 @@ static_assert(2 * kConsBatch <= kMaxSegs, "a consumer batch is at most 2 segment
 
 // One producer wave drives one stream: it takes as many of its next messages
 // as the ring has room for (up to kProdBatch, or kProdBatchLocking), copies
-// them as one batch, writes their entries and publishes them with one release.
+// them as one batch and writes their entries.  A locking ring publishes every
+// batch (in reservation order).  On a ring of its own, a stream of more than
+// four rings' worth of entries keeps full batches unpublished, up to
+// E / kProdBatch of them, and publishes them with one release; when the next
+// message does not fit, it publishes what it holds before it waits (the
+// consumer cannot free room for messages it has not seen).  Measured on the
+// channel configuration (~650 messages per stream), one process alternating:
+// 3,564-3,680 GB/s holding up to four batches against 2,873-3,207 with a
+// release per batch, message latency p99 0.9 ms against 2.2-2.6 ms.  Short
+// streams publish every batch: holding in the serving loop's bursts (at most
+// 256 messages) raised its latency p99 from 1.9 to 3.1 ms, and holding only
+// while the consumer had a batch left to work on still to 2.3 ms, as a burst
+// loses the overlap of its producer and consumer.
 __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, Seg *sg) {
   // the stream id is the same in every lane of the wave; saying so lets the
   // stream and ring descriptors live in scalar registers
@@ -261,6 +276,25 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, 
   w.progress();
   uint64_t m = 0;
   uint64_t out_run = 0;  // output bytes of this stream's earlier messages
+  const uint64_t max_held =
+      locking || st.n_msgs <= 4 * r.E ? 1 : (r.E / kProdBatch > 1 ? r.E / kProdBatch : 1);
+  uint64_t pub_m = 0;  // messages published
+  uint64_t held = 0;   // full batches copied and not yet published
+  // the release covers the payload and entries of every message since the
+  // last publication; then the counters move past them
+  auto publish = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (a.ts_push)
+      for (uint64_t k = lane; k < m - pub_m; k += 64) a.ts_push[st.first_msg + pub_m + k] = wall_clock64();
+    if (lane == 0) {
+      // a ring of its own also publishes its byte counter, the form user
+      // kernels (hicr_device.h) resume from
+      st_rlx(tm_a + 8, tb);
+      st_rlx(tm_a, tm);
+    }
+    pub_m = m;
+    held = 0;
+  };
   while (m < st.n_msgs) {
     // sizes and offsets of the next messages of this batch, one per lane
     const bool have = lane < (locking ? kProdBatchLocking : kProdBatch) && m + lane < st.n_msgs;
@@ -300,6 +334,7 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, 
       hm = shfl64(ld_rlx(hm_a), 0);  // one view of the consumer for the whole wave
       hb = shfl64(ld_rlx(hb_a), 0);
       if (my_tm - hm < r.E && my_tb - hb + s0 <= r.P) break;
+      if (held) publish();
       __builtin_amdgcn_s_sleep(2);
       if (w.expired()) return;
     }
@@ -353,21 +388,20 @@ __device__ void run_producer(const PumpArgs &a, uint32_t sid_in, uint32_t lane, 
         if (w.expired()) return;
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-    } else {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (a.ts_push && lane < j) a.ts_push[st.first_msg + m + lane] = wall_clock64();
+      if (lane == 0) st_rlx(tm_a, my_tm + j);
     }
-    if (a.ts_push && lane < j) a.ts_push[st.first_msg + m + lane] = wall_clock64();
-    if (lane == 0) {
-      // a ring of its own also publishes its byte counter, the form user
-      // kernels (hicr_device.h) resume from
-      if (!locking) st_rlx(tm_a + 8, my_tb + bytes);
-      st_rlx(tm_a, my_tm + j);
-    }
-    wave_sync();
     tm = my_tm + j;
     tb = my_tb + bytes;
     m += j;
     out_run += bytes;
+    if (!locking) {
+      if (held + 1 < max_held && j == kProdBatch && m < st.n_msgs)
+        held++;
+      else
+        publish();
+    }
+    wave_sync();
     w.progress();
   }
 }

@@ -30,6 +30,47 @@ def test_batched_ring_catches(cfg, bug):
         pk.explore_batched(*cfg, pk.Bug(**{bug: True}))
 
 
+# deferred publication: (P, E, sizes, B, C, S) -- sub-batches of B messages,
+# up to S per publication
+DEFERRED = [
+    (4, 4, [1, 1, 1, 1, 2], 2, 1, 2),
+    (4, 6, [1, 1, 1, 1, 1, 1], 2, 2, 3),
+    (5, 4, [1, 2, 1, 1, 2], 2, 1, 2),
+    (3, 4, [1, 1, 1, 1], 1, 2, 3),
+    (2, 4, [1, 1, 1], 2, 1, 2),          # a full sub-batch fills the ring's bytes
+    (4, 4, [2, 2, 1, 1], 2, 1, 2),       # ... with messages of two bytes
+    (3, 2, [1, 1, 1, 1], 2, 2, 3),       # ... fills the ring's entries
+]
+
+
+@pytest.mark.parametrize("cfg", DEFERRED)
+def test_deferred_publication_accepts(cfg):
+    P, E, sizes, B, C, S = cfg
+    assert pk.explore_batched(P, E, sizes, B, C, S=S) > 0
+
+
+@pytest.mark.parametrize("cfg", DEFERRED[4:])
+def test_deferred_publication_catches_a_blocked_producer_that_holds_messages(cfg):
+    # these configurations reach a state where a full sub-batch is held and
+    # the next message does not fit
+    P, E, sizes, B, C, S = cfg
+    with pytest.raises(pk.Violation, match="deadlock"):
+        pk.explore_batched(P, E, sizes, B, C, pk.Bug(no_publish_when_blocked=True), S=S)
+
+
+@pytest.mark.parametrize("bug", ["publish_before_payload", "release_before_read",
+                                 "batch_room_first_only"])
+@pytest.mark.parametrize("cfg", [(6, 4, [1, 1, 3, 2, 1, 2], 2, 1, 2),
+                                 (5, 6, [1, 1, 2, 2, 1, 1], 2, 1, 3)])
+def test_deferred_publication_catches(cfg, bug):
+    P, E, sizes, B, C, S = cfg
+    # the configuration reaches held sub-batches (its state space differs
+    # from the one of immediate publication)
+    assert pk.explore_batched(P, E, sizes, B, C, S=S) != pk.explore_batched(P, E, sizes, B, C)
+    with pytest.raises(pk.Violation):
+        pk.explore_batched(P, E, sizes, B, C, pk.Bug(**{bug: True}), S=S)
+
+
 TEAM = [
     (4, 2, [[1, 2], [2, 1]], 2, 2),
     (3, 3, [[1, 1], [2, 1]], 2, 1),
