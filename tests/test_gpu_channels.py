@@ -424,6 +424,37 @@ def test_pump_odd_ring_sizes(env, mode):
 
 
 @pytest.mark.parametrize("mode", ["lock", "nolock"])
+@pytest.mark.parametrize("sizes", ["fixed", "mixed"])
+def test_pump_held_batches_fill_the_ring(env, mode, sizes):
+    """Streams of 320 messages, longer than four rings' worth of entries
+    (E = 64), so the producers of rings of their own hold full batches of 16
+    and publish up to 64 messages per release.  With 4 KiB messages through
+    128 KiB rings two held batches fill a ring, so every third batch finds no
+    room and has to publish the held ones before it waits; with sizes of
+    1 B..8 KiB the ring fills at varying points.  The same bytes as the
+    oracle, every stream whole."""
+    torch, H, wd, ctx = env
+    from bench import channel_rig
+    seed = 417
+    _say("pump held batches", mode, sizes)
+    lo, hi = (4096, 4096) if sizes == "fixed" else (1, 8192)
+    plan = wc.plan(n_spsc=8, n_mpsc=2, K=3, total_msgs=14 * 320, lo=lo, hi=hi, P=32 * 4096,
+                   E=64, src_bytes=1 << 20, batch=11)
+    assert int(np.diff(plan.msg_begin).min()) > 4 * 64
+    hmode = H.CH_MPSC_LOCK if mode == "lock" else H.CH_MPSC_NOLOCK
+    rig = channel_rig(torch, H, ctx, plan, hmode, seed)
+    trace = torch.zeros(plan.n_msgs, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    rc = H.hicr_channel_pump(ctx, rig["streams"], plan.msg_src_off, plan.msg_size,
+                             trace.data_ptr(), 0, timeout_ns=5 * 10**9)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK, H.hicr_last_error(ctx)
+    _check_plan(torch, H, rig, plan, seed, mode, trace)
+    for ch in rig["channels"]:
+        assert H.hicr_channel_destroy(ch) == H.OK
+
+
+@pytest.mark.parametrize("mode", ["lock", "nolock"])
 def test_pump_device_tables(env, mode):
     """The small mixed plan with its message tables in device memory
     (HICR_PUMP_DEVICE_TABLES): the same bytes as the oracle, every message
