@@ -527,9 +527,23 @@ def bench_pingpong(torch, H, max_log2=31, reps=10):
     return rows
 
 
+# The batched line's schedule: a fixed schedule, not one of the 12 classes
+# (whose chunks are 4 KiB, 64 KiB and 1 MiB): 32 KiB pieces, at least one per
+# request, unroll 4.  In-process sweeps of the chunk size on this workload
+# (one pool allocation, the library default grid, batches 0-3): 8 KiB 5,135,
+# 16 KiB 5,157, 24 KiB 5,070, 32 KiB 5,740, 40 KiB 5,050, 48 KiB 5,185,
+# 64 KiB (class 5) 5,420, 128 KiB 5,085, 1 MiB 4,680 GB/s.
+BATCHED_SCHED = "32768,1,4"
+
+
 def parse_sched(H, text):
+    """A schedule class number, "tuned", "learned", or "chunk,wgs,unroll"
+    (a fixed schedule)."""
     if text in ("tuned", "learned"):
         return H.make_sched(64 << 10, 1, 2, H.SCHED_TUNED if text == "tuned" else H.SCHED_LEARNED)
+    if "," in text:
+        chunk, wgs, unroll = (int(x) for x in text.split(","))
+        return H.make_sched(chunk, wgs, unroll)
     rc, s = H.hicr_sched_class(int(text))
     assert rc == H.OK
     return s
@@ -804,7 +818,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sched", default="5")
+    ap.add_argument("--sched", default=BATCHED_SCHED,
+                    help="class number, tuned, learned, or chunk,wgs,unroll")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-channels", action="store_true")
@@ -932,7 +947,10 @@ def main():
                                "slot windows (72 MiB at 8 MiB stride) over a 64 GiB + 64 MiB "
                                "pool, one fused launch + fence per batch",
                    "requests_per_batch": 4096, "slots": 8192, "pool_bytes": wm.B_POOL,
-                   "schedule": args.sched, "copy_wgs_per_cu": args.copy_grid or "library default for the class",
+                   "schedule": (args.sched if "," not in args.sched else
+                                "fixed: {} B chunks, at least {} piece(s) per request, unroll {}"
+                                .format(*args.sched.split(","))),
+                   "copy_wgs_per_cu": args.copy_grid or "library default for the schedule",
                    "gb_per_batch_rw": round(float(np.mean(moved)) / 1e9, 3)},
         "p50_ms": round(float(np.percentile(step_s, 50)) * 1e3, 4),
         "p99_ms": round(float(np.percentile(step_s, 99)) * 1e3, 4),

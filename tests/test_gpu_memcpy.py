@@ -470,10 +470,12 @@ def test_single_request_over_4gib(env):
 
 
 @pytest.mark.timeout(900)
-def test_batched_full_size_whole(env):
+@pytest.mark.parametrize("sched_text", ["bench", "5"])
+def test_batched_full_size_whole(env, sched_text):
     """One batch of the measured configuration (8,192 slot windows over a
     64 GiB + 64 MiB pool, 4,096 requests, ~22 GB) in exactly the launch the
-    benchmark times: class 5 and the library's default grid.  Every
+    benchmark times (its fixed schedule and the library's default grid), and
+    under class 5.  Every
     destination range, with 64 bytes of margin on each side, is compared
     with the oracle; so are at least 1 GiB of untouched bytes sampled from
     the gaps between destinations, and all 8,192 slot counters."""
@@ -487,8 +489,9 @@ def test_batched_full_size_whole(env):
     slots = _register_pool(H, ctx, pool, bases, sizes)
     descs = wm.batched(0)
     assert H.hicr_ctx_set_copy_grid(ctx, 0) == H.OK
-    rc, sched = H.hicr_sched_class(5)
-    _say("batched full size: submit")
+    import bench
+    sched = bench.parse_sched(H, bench.BATCHED_SCHED if sched_text == "bench" else sched_text)
+    _say("batched full size: submit", sched_text)
     rc, bad = H.hicr_memcpy_batch(ctx, _remap(descs, slots), sched)
     assert rc == H.OK, H.hicr_last_error(ctx)
     assert H.hicr_fence(ctx) == H.OK
