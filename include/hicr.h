@@ -129,8 +129,10 @@ int hicr_last_error(hicr_ctx ctx, char *buf, size_t n);
 int hicr_ctx_set_sched(hicr_ctx ctx, const hicr_sched *s);
 /* Copy workgroups launched per compute unit (the persistent grid is at most
  * CUs x this, capped by what fits).  0 (the default) picks by schedule: 4 for
- * 4 KiB chunks, otherwise 2; at least 4 for a launch of more than 4,096
- * requests whose average piece is under 16 KiB.  Never changes a byte.
+ * chunks of 4 KiB or less, 1 for chunks above 16 KiB up to 32 KiB, otherwise
+ * 2; at least 4 for a launch of more than 4,096 requests whose chunks are
+ * 16 KiB or less or whose average request is under 16 KiB.  Never changes a
+ * byte.
  * wgs_per_cu > 64 -> HICR_EINVAL. */
 int hicr_ctx_set_copy_grid(hicr_ctx ctx, uint32_t wgs_per_cu);
 /* Memory-space pairs memcpy accepts from now on (HICR_PAIR bits; default

@@ -161,9 +161,14 @@ static int alloc_counters(hicr_ctx c) {
 // batched workload (256 CUs): with 64 KiB or 1 MiB pieces two workgroups per
 // CU (eight wavefronts, each with two rounds of `unroll` 1 KiB rows in
 // flight) are the fastest at either unroll, 1-2 % above one or four; 4 KiB
-// pieces spend more time per piece on the search and want four.
+// pieces spend more time per piece on the search and want four.  32 KiB
+// pieces at unroll 4 run 1.7 % faster with one workgroup per CU than with
+// two (0.6-1 % on 64 MiB copies, aligned or not); 24 KiB pieces tie, 48 KiB
+// pieces lose 0.6 %.  Pieces of 16 KiB or less get at least four from the
+// latency rule in launch_copies.
 int default_grid_per_cu(const DevSched &ds) {
   if (ds.chunk <= (4u << 10)) return 4;
+  if (ds.chunk <= (32u << 10)) return 1;
   return 2;
 }
 
