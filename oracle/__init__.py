@@ -36,8 +36,8 @@ EHAZARD = -8
 
 MEM_HBM = 0
 MEM_HOST = 1
-# Only HBM -> HBM transfers are supported by the GPU library; the oracle is
-# created with the same pair matrix by default.
+# A context accepts HBM -> HBM transfers unless created with another pair
+# matrix (bit 2 * dst_space + src_space; 0b1111 accepts every pair).
 PAIR_HBM_HBM = 1 << (2 * MEM_HBM + MEM_HBM)
 
 DESC_DTYPE = np.dtype(

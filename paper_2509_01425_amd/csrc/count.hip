@@ -15,8 +15,13 @@ namespace hicr {
 // received in 16..31 -- at most 1,024 requests per group); a slot whose
 // bucket another slot holds goes straight to device memory.  Slot ids are
 // below 2^20, never ~0u.
+// done != null (one-group launches only): once every wave's counter
+// atomics have completed, the group stores seq to *done (host memory) at
+// system scope, so that a host waiting for the submission can see its end
+// without waiting for the runtime's completion signal.
 __global__ __launch_bounds__(kCopyBlock) void count_kernel(const uint64_t *slots, uint64_t n,
-                                                           uint64_t *counters) {
+                                                           uint64_t *counters, uint64_t *done,
+                                                           uint64_t seq) {
   constexpr uint32_t kBuckets = 2048;
   constexpr uint32_t kPerGroup = 1024;  // requests per group: short serial chains
   constexpr uint32_t kEmpty = 0xffffffffu;
@@ -77,16 +82,27 @@ __global__ __launch_bounds__(kCopyBlock) void count_kernel(const uint64_t *slots
       __hip_atomic_fetch_add(&counters[2 * (uint64_t)k + 1], (uint64_t)(c >> 16),
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (done) {
+    // each wave's release orders its own atomics before the barrier; the
+    // store's system-scope release then carries them all to the host
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(done, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
-hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters,
-                        hipStream_t stream) {
+hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters, hipStream_t stream,
+                        uint64_t *done, uint64_t seq, bool *armed) {
+  if (armed) *armed = false;
   if (n == 0) return hipSuccess;
   const uint64_t groups = (n + 1023) / 1024;
   if (groups > 0x7fffffffull) return hipErrorInvalidValue;
+  uint64_t *d = groups == 1 ? done : nullptr;
   hipLaunchKernelGGL(count_kernel, dim3((uint32_t)groups), dim3(kCopyBlock), 0, stream, slots, n,
-                     counters);
-  return hipGetLastError();
+                     counters, d, seq);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && armed) *armed = d != nullptr;
+  return e;
 }
 
 }  // namespace hicr

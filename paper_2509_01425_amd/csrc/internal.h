@@ -73,9 +73,11 @@ hipError_t launch_scan(const DevBatch &b, DevSched s, uint32_t *ends, uint32_t *
 hipError_t launch_copy_mem(const DevBatch &b, DevSched s, const uint32_t *ends,
                            const uint32_t *tile_tot, uint32_t grid, hipStream_t stream);
 // Raise the slot counters of n requests (slots[i] = dst | src << 32); queued
-// after the copy launches of the same requests on the same stream.
-hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters,
-                        hipStream_t stream);
+// after the copy launches of the same requests on the same stream.  When the
+// launch is a single workgroup (n <= 1,024) and done is not null, the kernel
+// ends by storing seq to *done (pinned host memory) and *armed is set.
+hipError_t launch_count(const uint64_t *slots, uint64_t n, uint64_t *counters, hipStream_t stream,
+                        uint64_t *done = nullptr, uint64_t seq = 0, bool *armed = nullptr);
 // Workgroups of the copy kernel that one CU holds at once.
 int copy_occupancy(int *wgs_per_cu);
 

@@ -32,6 +32,12 @@ struct hicr_plan_s {
   hipStream_t last = nullptr; // stream of the last replay
   bool launched = false;
   std::vector<hicr_slot> slots;  // distinct slots the requests name
+  // direct replays of a plan that writes device memory only and has one
+  // counter group: the pinned word their counter kernel stores the replay's
+  // number to, the number of the last replay, and whether it will be stored
+  uint64_t *h_done = nullptr;
+  uint64_t done_seq = 0;
+  bool done_armed = false;
 };
 
 namespace {
@@ -41,12 +47,17 @@ void free_plan(hicr_plan p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->ev) (void)hipEventDestroy(p->ev);
   if (p->d) (void)hipFree(p->d);
+  if (p->h_done) (void)hipHostFree(p->h_done);
   for (hicr_slot s : p->slots) p->c->slots[s].plan_refs--;
   delete p;
 }
 
 int wait_plan(hicr_ctx c, hicr_plan p) {
   if (!p->launched) return HICR_OK;
+  if (p->done_armed && wait_done(p->h_done, p->done_seq)) {
+    p->launched = false;
+    return HICR_OK;
+  }
   hipError_t e = sync_event(p->ev);
   p->launched = false;
   return e == hipSuccess ? HICR_OK : hip_fail(c, e, "waiting for a plan replay");
@@ -68,7 +79,8 @@ int wait_plans(hicr_ctx c) {
 bool plans_inflight(hicr_ctx c) {
   for (hicr_plan p : c->plans) {
     if (!p->launched) continue;
-    if (hipEventQuery(p->ev) == hipSuccess)
+    if ((p->done_armed && __atomic_load_n(p->h_done, __ATOMIC_ACQUIRE) == p->done_seq) ||
+        hipEventQuery(p->ev) == hipSuccess)
       p->launched = false;
     else
       return true;
@@ -140,6 +152,11 @@ int hicr_plan_create(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sche
     }
     hipStream_t cs = nullptr;
     hipError_t e = hipEventCreateWithFlags(&p->ev, hipEventDisableTiming);
+    if (e == hipSuccess && n && n <= 1024 && !(flags & HICR_PLAN_GRAPH) &&
+        writes_device_only(c, d, n)) {
+      e = hipHostMalloc(&p->h_done, 64, hipHostMallocDefault);
+      if (e == hipSuccess) *p->h_done = 0;
+    }
     if (e == hipSuccess && n) e = hipMalloc(&p->d, batch_bytes(n));
     if (e == hipSuccess && n) e = hipMemcpy(p->d, h.data(), n * 32, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -201,9 +218,18 @@ int hicr_plan_launch(hicr_plan p, void *stream) {
       e = hipGraphLaunch(p->exec, s);
     } else if (e == hipSuccess && p->n) {
       const uint64_t *dd = static_cast<const uint64_t *>(p->d);
-      int rc =
-          launch_copies(c, dd, p->n, p->segs, p->ds, batch_tables(p->d, p->n), c->d_counters, s);
+      // replays are ordered (same stream, or the wait above), so the word's
+      // last value is the last replay's
+      const uint64_t seq = p->done_seq + 1;
+      bool armed = false;
+      p->done_armed = false;
+      int rc = launch_copies(c, dd, p->n, p->segs, p->ds, batch_tables(p->d, p->n), c->d_counters,
+                             s, p->h_done, seq, &armed);
       if (rc != HICR_OK) return rc;
+      if (armed) {
+        p->done_seq = seq;
+        p->done_armed = true;
+      }
     }
     if (e == hipSuccess) e = hipEventRecord(p->ev, s);
     if (e != hipSuccess) return hip_fail(c, e, "launching a plan");

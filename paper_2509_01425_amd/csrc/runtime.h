@@ -26,7 +26,8 @@ struct Slot {
 };
 
 // One submission buffer: pinned staging, its device copy, the event that
-// marks the end of the submission, and the finished-workgroup counter.
+// marks the end of the submission, and the value its counter kernel stores
+// to the buffer's word of the context's done array when it ends.
 struct Sub {
   void *h = nullptr;
   void *d = nullptr;
@@ -34,6 +35,7 @@ struct Sub {
   hipEvent_t ev = nullptr;     // end of the submission's last launch
   hipEvent_t up_ev = nullptr;  // end of its upload, when that ran on the upload stream
   bool inflight = false;
+  uint64_t done_seq = 0;       // 0: the submission raises no done word
 };
 
 class HostPool;  // host threads that validate and pack large batches (runtime.cpp)
@@ -109,6 +111,11 @@ struct hicr_ctx_s {
   uint64_t *h_read = nullptr;  // pinned read-back buffer
   hicr::Sub subs[hicr::kNumSubs];
   int next_sub = 0;
+  // pinned words that one-group counter launches raise when a submission
+  // ends (word 8 i for subs[i], one 64-byte line each), and the last value
+  // handed out
+  uint64_t *h_done = nullptr;
+  uint64_t done_next = 0;
   // hicr_memcpy_batch_noalloc: this device's fixed workspace, pinned staging
   // allocated with the context, and the events of the last such submission
   void *na_scratch = nullptr;
@@ -146,6 +153,13 @@ int check_sched(hicr_ctx c, const hicr_sched &s);
 bool any_inflight(hicr_ctx c);
 // Wait for an event: poll briefly, then block.
 hipError_t sync_event(hipEvent_t e);
+// Poll a done word (pinned host memory a counter kernel stores to) for up
+// to 200 us; true once it holds seq.
+bool wait_done(const uint64_t *w, uint64_t seq);
+// Whether every request of a batch writes device memory (HBM slots): only
+// then may a done word stand for the end of the batch, since the runtime's
+// completion signal is what makes bytes written to host memory visible.
+bool writes_device_only(hicr_ctx c, const hicr_desc *d, uint64_t n);
 int wait_all(hicr_ctx c);
 int submit(hicr_ctx c, const hicr_desc *d, uint64_t n, const hicr_sched &sched,
            hipStream_t stream, uint64_t *bad, const SubmitOpts *opt);
@@ -162,9 +176,12 @@ int split_batch(hicr_ctx c, const uint64_t *hd, const uint64_t *hz, uint64_t n, 
 // batch_tables() region beside the uploaded batch dd).
 int launch_scans(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
                  DevSched ds, uint32_t *tables, hipStream_t stream);
-// Queue the copy launches, then (counters != null) the counter kernel.
+// Queue the copy launches, then (counters != null) the counter kernel; with
+// done != null a one-group counter launch ends by storing seq to *done, and
+// *armed says whether it will.
 int launch_copies(hicr_ctx c, const uint64_t *dd, uint64_t n, const std::vector<Seg> &segs,
-                  DevSched ds, const uint32_t *tables, uint64_t *counters, hipStream_t stream);
+                  DevSched ds, const uint32_t *tables, uint64_t *counters, hipStream_t stream,
+                  uint64_t *done = nullptr, uint64_t seq = 0, bool *armed = nullptr);
 // Bytes of device memory an uploaded batch of n requests takes: the packed
 // requests (32 B each), then the piece tables: per-request prefixes (4 B
 // each) and tile totals (a launch over requests [i0, i1) keeps its tiles at

@@ -394,6 +394,98 @@ def test_single_memcpy_broadcast_and_fence_slot(env):
     assert H.hicr_fence_slot(ctx, dslots[0], 0, 1, 10**6) == H.OK
 
 
+def test_fence_after_chained_small_batches(env):
+    """A fence that returns once a small batch's counter kernel has raised its
+    done word must still leave every byte and counter visible.  A chain of
+    batches, each reading the region the previous one wrote, with 1 to 1,025
+    requests (1,024 is the largest batch with one counter group), fences after
+    one batch or after five (every submission buffer in flight), and every
+    fifth batch written to pinned host memory (the event decides there).
+    After every fence the pool is read on torch's stream and the counters on
+    the library's counter stream, both compared with the oracle applying the
+    same chain; then a plan of 600 requests replayed directly 40 times, with a
+    fence after every 1 to 3 replays, keeps every counter at the number of
+    replays queued."""
+    torch, H, wd, ctx = env
+    R, cell = 512 << 10, 256
+    seed = 99
+    _say("chained small batches")
+    pool = torch.empty(3 * R, dtype=torch.uint8, device="cuda")
+    wd.fill(pool.data_ptr(), 3 * R, seed)
+    torch.cuda.synchronize()
+    hostbuf = torch.zeros(R, dtype=torch.uint8).pin_memory()
+    rc, sp = H.hicr_slot_register(ctx, pool.data_ptr(), 3 * R, H.MEM_HBM)
+    rc2, sh = H.hicr_slot_register(ctx, hostbuf.data_ptr(), R, H.MEM_HOST)
+    assert rc == rc2 == H.OK
+    want = content(seed, 0, 3 * R)
+    want_h = np.zeros(R, dtype=np.uint8)
+    oc = oracle.Ctx(pair_mask=0b1111)
+    op = oc.register(want, offset=0, size=3 * R)[1]
+    oh = oc.register(want_h, offset=0, size=R, space=oracle.MEM_HOST)[1]
+    g = np.random.default_rng(7)
+    sizes = [1, 7, 256, 1000, 1024, 1025, 64, 3]
+    queued = 0
+    for k in range(40):
+        group = 5 if k % 7 == 3 else 1
+        for j in range(group):
+            it = k * 5 + j
+            m = sizes[it % len(sizes)]
+            to_host = it % 5 == 4
+            src_r, dst_r = it % 3, (it + 1) % 3
+            d = np.zeros(m, dtype=H.DESC_DTYPE)
+            d["src_slot"] = sp
+            d["src_off"] = src_r * R + g.integers(0, R - cell, m)
+            cells = g.permutation(R // cell)[:m]
+            d["size"] = g.integers(0, 200, m)
+            off = cells * cell + g.integers(0, cell - 200, m)
+            if to_host:
+                d["dst_slot"], d["dst_off"] = sh, off
+            else:
+                d["dst_slot"], d["dst_off"] = sp, dst_r * R + off
+            rc, bad = H.hicr_memcpy_batch(ctx, d)
+            assert rc == H.OK, H.hicr_last_error(ctx)
+            od = d.copy()
+            od["src_slot"] = op
+            od["dst_slot"] = oh if to_host else op
+            assert oc.memcpy_batch(od)[0] == oracle.OK
+            queued += m
+        assert H.hicr_fence(ctx) == H.OK
+        got = pool.cpu().numpy()
+        assert np.array_equal(got, want), (k, np.nonzero(got != want)[0][:8])
+        assert np.array_equal(hostbuf.numpy(), want_h), k
+        assert H.hicr_slot_counters(ctx, sp)[1:] == oc.counters(op)[1:], k
+        assert H.hicr_slot_counters(ctx, sh)[1:] == oc.counters(oh)[1:], k
+    # a plan with one counter group replayed directly
+    n = 600
+    d = np.zeros(n, dtype=H.DESC_DTYPE)
+    rc, a = H.hicr_slot_register(ctx, pool.data_ptr(), R, H.MEM_HBM)
+    rc2, b = H.hicr_slot_register(ctx, pool.data_ptr() + R, R, H.MEM_HBM)
+    assert rc == rc2 == H.OK
+    d["dst_slot"], d["src_slot"] = b, a
+    d["dst_off"] = g.permutation(R // cell)[:n] * cell
+    d["src_off"] = g.integers(0, R - cell, n)
+    d["size"] = g.integers(1, cell, n)
+    rc, plan, _ = H.hicr_plan_create(ctx, d, None, 0)
+    assert rc == H.OK, H.hicr_last_error(ctx)
+    od = d.copy()
+    od["dst_slot"], od["src_slot"] = op, op
+    od["dst_off"] += R
+    assert oc.memcpy_batch(od)[0] == oracle.OK
+    replays = 0
+    while replays < 40:
+        for _ in range(1 + replays % 3):
+            assert H.hicr_plan_launch(plan, 0) == H.OK
+            replays += 1
+        assert H.hicr_fence(ctx) == H.OK
+        assert H.hicr_slot_counters(ctx, a) == (H.OK, replays * n, 0), replays
+        assert H.hicr_slot_counters(ctx, b) == (H.OK, 0, replays * n), replays
+        got = pool.cpu().numpy()
+        assert np.array_equal(got, want), (replays, np.nonzero(got != want)[0][:8])
+    assert H.hicr_plan_destroy(plan) == H.OK
+    for sl in (a, b, sp, sh):
+        assert H.hicr_slot_deregister(ctx, sl) == H.OK
+
+
 def test_rejections_enqueue_nothing(env):
     torch, H, wd, ctx = env
     _say("rejections")
