@@ -446,7 +446,12 @@ typedef struct {
  * device are not coordinated. */
 int hicr_channel_pump(hicr_ctx ctx, const hicr_stream *streams, uint32_t n_streams,
                       const hicr_pump_io *io, void *stream);
-/* Ask running pumps of this context to stop (they end at their next wait). */
+/* Ask running pumps of this context to stop (they end at their next wait;
+ * a waiting wave reads the request within ~10 ms of its own waiting, the
+ * waves staggered, and passes it on to the others within 10 us).  A store
+ * into each pump's pinned abort word:
+ * it never waits for the device, and it reaches a pump even when every
+ * stream of the process shares the pump's hardware queue. */
 int hicr_channel_abort(hicr_ctx ctx);
 
 /* Device view of one ring, for producers and consumers written in the

@@ -107,7 +107,8 @@ struct PumpArgs {
   uint32_t *trace;     // nullable: stream index of each consumed message, per channel order
   uint64_t *ts_push;   // nullable: wall clock (100 MHz) when each message was published
   uint64_t *ts_pop;    // nullable: wall clock when each message was consumed
-  uint32_t *err;       // err[0] error bits, err[1] abort request
+  uint32_t *err;       // err[0] error bits, err[1] abort request, err[4..5] address of
+                       // the host's abort word (pinned; nonzero asks the pump to stop)
   uint64_t timeout_ticks;
 };
 

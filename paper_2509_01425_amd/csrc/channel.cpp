@@ -22,6 +22,11 @@
 
 using namespace hicr;
 
+// Offset of a pump's abort word in its pinned staging: inside the 256-byte
+// head that every launch zeroes, past the 8 bytes of error words that come
+// back from the device at the end.
+constexpr uint64_t kAbortHostOff = 128;
+
 struct hicr_channel_s {
   hicr_ctx ctx = nullptr;
   hicr_channel_cfg cfg{};
@@ -660,6 +665,11 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
   }
   char *h = static_cast<char *>(x.h_buf);
   std::memset(h, 0, 256);
+  // the host's abort request: a word of the pinned staging's zeroed head,
+  // which nothing else writes while the pump runs; its address goes up with
+  // the error words (err[4..5])
+  const uint64_t abort_addr = reinterpret_cast<uint64_t>(h + kAbortHostOff);
+  std::memcpy(h + o_err + 16, &abort_addr, 8);
   std::memcpy(h + o_ring, rings.data(), rings.size() * sizeof(DevRing));
   std::memcpy(h + o_ch, dch.data(), dch.size() * sizeof(DevChannel));
   std::memcpy(h + o_st, ds.data(), ds.size() * sizeof(DevStream));
@@ -716,7 +726,7 @@ int pump_launch(hicr_ctx c, const std::vector<PumpStream> &st, const uint64_t *m
     give_pump_buf(c, x);
     return hip_fail(c, e, "launching the channel pump");
   }
-  x.abort_word = a.err + 1;
+  x.abort_word = reinterpret_cast<uint32_t *>(h + kAbortHostOff);
   x.chans = chans;
   {
     PumpLive pl;
@@ -842,13 +852,11 @@ int hicr_channel_abort(hicr_ctx c) {
   return guarded([&]() -> int {
     if (!c) return HICR_EINVAL;
     std::lock_guard<std::mutex> g(c->abort_mu);  // not c->mu: a fence may hold it
-    (void)hipSetDevice(c->device);
-    static const uint32_t one = 1;
-    for (uint32_t *w : c->abort_words) {
-      hipError_t e = hipMemcpyAsync(w, &one, 4, hipMemcpyHostToDevice, c->abort_stream);
-      if (e != hipSuccess) return fail(nullptr, HICR_EDEVICE, "abort");
-    }
-    return hipStreamSynchronize(c->abort_stream) == hipSuccess ? HICR_OK : HICR_EDEVICE;
+    // a store into each running pump's pinned abort word: no queue is
+    // involved, so the request cannot wait behind the pump it is meant to
+    // stop (streams share the device's few hardware queues)
+    for (uint32_t *w : c->abort_words) __atomic_store_n(w, 1u, __ATOMIC_RELEASE);
+    return HICR_OK;
   });
 }
 

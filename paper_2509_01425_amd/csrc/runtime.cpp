@@ -571,7 +571,6 @@ int hicr_ctx_create(int device, void *stream, hicr_ctx *out) {
     ok = ok && hipHostMalloc(&c->h_read, 64, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipHostMalloc(&c->h_done, 64 * kNumSubs, hipHostMallocDefault) == hipSuccess;
     if (ok) std::memset(c->h_done, 0, 64 * kNumSubs);
-    ok = ok && hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->push_ev, hipEventDisableTiming) == hipSuccess;
     if (ok && (pump_occupancy(&c->pump_occ) != 0 || c->pump_occ < 1)) c->pump_occ = 1;
     ok = ok && hipStreamCreateWithFlags(&c->up, hipStreamNonBlocking) == hipSuccess;
@@ -624,7 +623,6 @@ int hicr_ctx_destroy(hicr_ctx c) {
     if (c->na_ev) (void)hipEventDestroy(c->na_ev);
     if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->up) (void)hipStreamDestroy(c->up);
-    if (c->abort_stream) (void)hipStreamDestroy(c->abort_stream);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return HICR_OK;

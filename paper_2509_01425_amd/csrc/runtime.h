@@ -139,8 +139,7 @@ struct hicr_ctx_s {
   hipEvent_t push_ev = nullptr;  // last host-API channel push or network step
   bool push_pending = false;
   std::mutex abort_mu;  // guards abort_words; never held while waiting on the GPU
-  std::vector<uint32_t *> abort_words;
-  hipStream_t abort_stream = nullptr;
+  std::vector<uint32_t *> abort_words;  // running pumps' pinned abort words
   std::string err;
 };
 
