@@ -14,6 +14,7 @@ write bytes / time), per-step p50/p99, the copy kernel's roofline (event-
 timed on the stream it runs on) beside the box's reference copy, read and
 write streams, HBM traffic from committed rocprofv3 counters when they still
 match the kernel source; then the channel pumps (both MPSC modes), the
+tiny batch's submit-to-fence latency (memcpy_batch and plan replays), the
 serving loop (60 s of Poisson arrivals at 2,000 requests/s, 200 GB budget),
 the learned schedule (a 2,000 + 200 batch version of the 20,000 + 1,000
 configuration, which `--workload learned` runs whole), and the CPU oracle's
@@ -834,6 +835,7 @@ def main():
     ap.add_argument("--learned-test", type=int, default=1000)
     ap.add_argument("--learned-save", default=None)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-tiny", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--line-learned-train", type=int, default=2000,
                     help="training batches of the learned-schedule part of the default line")
@@ -966,6 +968,9 @@ def main():
     if not args.no_channels:
         out["channels"] = [bench_channels(torch, H, m) for m in (H.CH_MPSC_LOCK, H.CH_MPSC_NOLOCK)]
         progress("channels measured")
+    if not args.no_tiny:
+        out["tiny"] = bench_tiny(torch, H)
+        progress("tiny batch latency measured")
     if not args.no_serving:
         sv = bench_serving(torch, H, duration_s=args.serve_seconds, budget=int(args.serve_budget))
         out["serving"] = {k: sv[k] for k in (
