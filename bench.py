@@ -531,9 +531,10 @@ def bench_pingpong(torch, H, max_log2=31, reps=10):
 # The batched line's schedule: a fixed schedule, not one of the 12 classes
 # (whose chunks are 4 KiB, 64 KiB and 1 MiB): 32 KiB pieces, at least one per
 # request, unroll 4.  In-process sweeps of the chunk size on this workload
-# (one pool allocation, the library default grid, batches 0-3): 8 KiB 5,135,
+# (one pool allocation, two workgroups per CU, batches 0-3): 8 KiB 5,135,
 # 16 KiB 5,157, 24 KiB 5,070, 32 KiB 5,740, 40 KiB 5,050, 48 KiB 5,185,
-# 64 KiB (class 5) 5,420, 128 KiB 5,085, 1 MiB 4,680 GB/s.
+# 64 KiB (class 5) 5,420, 128 KiB 5,085, 1 MiB 4,680 GB/s; 32 KiB at one
+# workgroup per CU (the library's default for that chunk) 5,823-5,857.
 BATCHED_SCHED = "32768,1,4"
 
 
