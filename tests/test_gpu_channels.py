@@ -625,3 +625,35 @@ def test_pump_abort_ends_a_running_pump(env):
     assert H.hicr_channel_pump(ctx, streams, offs, sizes) == H.EINVAL
     assert H.hicr_fence(ctx) == H.OK
     assert H.hicr_channel_destroy(ch) == H.OK
+
+
+def test_pump_abort_reaches_a_pump_that_shares_its_queue(env):
+    """hicr_channel_abort is a store into the pump's pinned abort word, so it
+    reaches a running pump whatever hardware queue the pump's stream shares:
+    the pump runs on one of twelve streams that all have had work (more
+    streams than the process's hardware queues), and ends early with the
+    abort reported."""
+    import time
+    torch, H, wd, ctx = env
+    _say("pump abort, twelve busy streams")
+    streams_t = [torch.cuda.Stream() for _ in range(12)]
+    busy = []
+    for st_ in streams_t:
+        with torch.cuda.stream(st_):
+            x = torch.zeros(1 << 16, device="cuda")
+            x += 1
+            busy.append(x)
+    torch.cuda.synchronize()
+    ch, streams, offs, sizes, keep = _blocking_rig(torch, H, wd, ctx, 60000, 4096, 8192, 4)
+    t0 = time.perf_counter()
+    assert H.hicr_channel_pump(ctx, streams, offs, sizes, timeout_ns=5 * 10**9,
+                               stream=streams_t[7].cuda_stream) == H.OK
+    time.sleep(0.002)
+    assert H.hicr_channel_abort(ctx) == H.OK
+    rc = H.hicr_fence(ctx)
+    dt = time.perf_counter() - t0
+    assert rc == H.EDEVICE, (rc, H.hicr_last_error(ctx), dt)
+    assert "abort" in H.hicr_last_error(ctx)
+    assert H.hicr_fence(ctx) == H.OK
+    assert H.hicr_channel_destroy(ch) == H.OK
+    torch.cuda.synchronize()
