@@ -24,6 +24,10 @@ scope, which give the same orders):
   messages), reads every message's ring position from the record its
   producer wrote before publishing, and releases the ring room in round
   order.
+* ``explore_batched_abort`` -- the same ring with an abort request that may
+  arrive at any moment: an actor that is waiting may then exit, one with
+  work in hand carries on to its next wait; no actor may be left waiting
+  forever (the pump's waits all look at its abort word).
 * ``explore_striped`` -- ping-pong between two groups of W members over two
   one-message rings whose counters count stripes: a message is visible when
   all W stripes have arrived (counter >= W (k + 1)), a ring is free when all
@@ -53,6 +57,8 @@ class Bug:
     count_messages: bool = False           # striped: counters waited on per message, not stripe
     signal_before_copy: bool = False       # striped: a stripe counted before it is copied
     no_publish_when_blocked: bool = False  # batched, S > 1: blocked with unpublished messages
+    abort_ignored_by_producer: bool = False  # abort: the producer's room wait never exits
+    abort_ignored_by_consumer: bool = False  # abort: the consumer's message wait never exits
 
 
 def _dfs(start, succ, done, max_states):
@@ -85,6 +91,61 @@ def explore_batched(P, E, sizes, B, C, bug=Bug(), max_states=3_000_000, S=1):
     and E entries; producer sub-batches of at most B messages, up to S of
     them per publication; consumer batches of at most C.  Returns the number
     of states visited."""
+    start, succ, done = _batched_model(P, E, sizes, B, C, bug, S)
+    return _dfs(start, succ, done, max_states)
+
+
+def explore_batched_abort(P, E, sizes, B, C, bug=Bug(), max_states=3_000_000, S=1):
+    """``explore_batched`` with an abort request that may arrive in any state.
+    Once it has arrived, an actor that has no move of its own -- a producer
+    waiting for room, a consumer waiting for messages: the waits in which a
+    kernel wave looks at its abort word -- may exit; an actor with work in
+    hand goes on to its next wait or to its end.  Every reachable state
+    keeps the safety checks of ``explore_batched``, and a state without
+    moves must have every actor finished or exited (no wave left waiting
+    forever).  Returns the number of states visited."""
+    n = len(sizes)
+    inner_start, inner_succ, inner_done = _batched_model(P, E, sizes, B, C, bug, S)
+
+    def prod_done(st):
+        return st[5][0] == n
+
+    def cons_done(st):
+        return st[8] == n
+
+    def succ(xst):
+        st, aborted, p_out, c_out = xst
+        p_moves, c_moves = [], []
+        for nx in inner_succ(st):
+            (p_moves if nx[5] != st[5] else c_moves).append(nx)
+        if not p_out:
+            for nx in p_moves:
+                yield (nx, aborted, p_out, c_out)
+        if not c_out:
+            for nx in c_moves:
+                yield (nx, aborted, p_out, c_out)
+        if not aborted:
+            yield (st, True, p_out, c_out)
+        else:
+            if (not p_out and not p_moves and not prod_done(st)
+                    and not bug.abort_ignored_by_producer):
+                yield (st, aborted, True, c_out)
+            if (not c_out and not c_moves and not cons_done(st)
+                    and not bug.abort_ignored_by_consumer):
+                yield (st, aborted, p_out, True)
+
+    def done(xst):
+        st, aborted, p_out, c_out = xst
+        if inner_done(st):
+            return True
+        return aborted and (p_out or prod_done(st)) and (c_out or cons_done(st))
+
+    return _dfs((inner_start, False, False, False), succ, done, max_states)
+
+
+def _batched_model(P, E, sizes, B, C, bug, S):
+    """Start state, successor function and end predicate of the batched
+    single-producer ring (see ``explore_batched``)."""
     n = len(sizes)
     offs = [sum(sizes[:i]) for i in range(n)]  # stream byte offset of message i
 
@@ -218,7 +279,7 @@ def explore_batched(P, E, sizes, B, C, bug=Bug(), max_states=3_000_000, S=1):
             raise Violation("entry capacity exceeded")
         return succ(st)
 
-    return _dfs(start, checked_succ, done, max_states)
+    return start, checked_succ, done
 
 
 # ------------------------------------------------- locking ring, team drain

@@ -30,6 +30,30 @@ def test_batched_ring_catches(cfg, bug):
         pk.explore_batched(*cfg, pk.Bug(**{bug: True}))
 
 
+# abort: every wave that waits looks at the pump's abort word, so once a
+# request has arrived no actor of a ring (Sec. 4.3) is left waiting; the
+# BATCHED rings, and two with deferred publication
+ABORT = [cfg + (1,) for cfg in BATCHED] + [(4, 4, [2, 2, 1, 1], 2, 1, 2), (3, 2, [1, 1, 1, 1], 2, 2, 3)]
+
+
+@pytest.mark.parametrize("cfg", ABORT)
+def test_abort_leaves_no_actor_waiting(cfg):
+    P, E, sizes, B, C, S = cfg
+    plain = pk.explore_batched(P, E, sizes, B, C, S=S)
+    # the abort adds states (a request in any state, exits from waits)
+    assert pk.explore_batched_abort(P, E, sizes, B, C, S=S) > plain
+
+
+@pytest.mark.parametrize("bug", ["abort_ignored_by_producer", "abort_ignored_by_consumer"])
+@pytest.mark.parametrize("cfg", ABORT)
+def test_abort_catches_a_wait_that_ignores_it(cfg, bug):
+    P, E, sizes, B, C, S = cfg
+    with pytest.raises(pk.Violation, match="deadlock"):
+        pk.explore_batched_abort(P, E, sizes, B, C, pk.Bug(**{bug: True}), S=S)
+    # the same bug changes nothing without an abort
+    assert pk.explore_batched(P, E, sizes, B, C, pk.Bug(**{bug: True}), S=S) > 0
+
+
 # deferred publication: (P, E, sizes, B, C, S) -- sub-batches of B messages,
 # up to S per publication
 DEFERRED = [
