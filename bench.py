@@ -953,7 +953,9 @@ def main():
                    "schedule": (args.sched if "," not in args.sched else
                                 "fixed: {} B chunks, at least {} piece(s) per request, unroll {}"
                                 .format(*args.sched.split(","))),
-                   "copy_wgs_per_cu": args.copy_grid or "library default for the schedule",
+                   "copy_wgs_per_cu": args.copy_grid or (
+                       "library default for the schedule: 4 for chunks of 4 KiB or less, 1 "
+                       "above 16 KiB up to 32 KiB, otherwise 2"),
                    "gb_per_batch_rw": round(float(np.mean(moved)) / 1e9, 3)},
         "p50_ms": round(float(np.percentile(step_s, 50)) * 1e3, 4),
         "p99_ms": round(float(np.percentile(step_s, 99)) * 1e3, 4),
