@@ -749,8 +749,37 @@ def bench_halo(torch, H, N=704, Py=2, Pz=22, h=2, iters=200, reps=3):
         assert rc == H.OK, H.hicr_last_error(ctx)
         out[name] = run(lambda: H.hicr_plan_launch(plan))
         assert H.hicr_plan_destroy(plan) == H.OK
+    # the same rows by a plain reference kernel (workloads/csrc/fill.hip: one
+    # wave per row, the whole row loaded before it is stored, no piece
+    # table), timed with events over `iters` launches, at a few grids
+    from workloads import device as wd
+    d0 = halo.exchange(N, Py, Pz, h)
+    row = int(d0["size"][0])
+    assert (d0["size"] == row).all() and row % 16 == 0
+    base = np.uint64(pool.data_ptr())
+    rows_dst = torch.from_numpy((base + d0["dst_slot"].astype(np.uint64) * np.uint64(sb)
+                                 + d0["dst_off"]).view(np.int64)).to("cuda")
+    rows_src = torch.from_numpy((base + d0["src_slot"].astype(np.uint64) * np.uint64(sb)
+                                 + d0["src_off"]).view(np.int64)).to("cuda")
+    torch.cuda.synchronize()
+    ref = {}
+    for blocks in (768, 2048, 4096):
+        def launch():
+            wd.ref_rows(rows_dst.data_ptr(), rows_src.data_ptr(), len(d0), row, blocks,
+                        stream.cuda_stream)
+        for _ in range(3):
+            launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(iters):
+            launch()
+        e1.record(stream)
+        e1.synchronize()
+        per = e0.elapsed_time(e1) * 1e-3 / iters
+        ref[str(blocks)] = {"us_per_exchange": round(per * 1e6, 2), "gbps": round(moved / per / 1e9, 1)}
+    out["reference_rows"] = ref
     H.hicr_ctx_destroy(ctx)
-    del pool
+    del pool, rows_dst, rows_src
     torch.cuda.empty_cache()
     return out
 

@@ -5,7 +5,7 @@
 // stream independently.  wl_ref_copy is a plain aligned 16-byte copy used as
 // the bandwidth reference for counter calibration; wl_ref_stream runs the
 // reference copy, read and write streams that bound what a copy reaches on
-// the box (measurement only).
+// the box, and wl_ref_rows a plain copy of a list of rows (measurement only).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -92,6 +92,25 @@ __global__ __launch_bounds__(256) void ref_copy_fast_kernel(uint64_t dst, uint64
   }
 }
 
+__global__ __launch_bounds__(256) void ref_rows_kernel(const uint64_t *dst_rows,
+                                                       const uint64_t *src_rows, uint32_t n_rows,
+                                                       uint32_t row16) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  for (uint32_t r = first; r < n_rows; r += gridDim.x * 4) {
+    const uint64_t d = dst_rows[r], s = src_rows[r];
+    v4u a[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+      if (lane + 64u * k < row16) a[k] = *(const GLOBAL v4u *)(s + 16ull * (lane + 64u * k));
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+      if (lane + 64u * k < row16)
+        __builtin_nontemporal_store(a[k], (GLOBAL v4u *)(d + 16ull * (lane + 64u * k)));
+  }
+}
+
 __global__ __launch_bounds__(256) void ref_read_kernel(uint64_t src, uint32_t pieces,
                                                        uint32_t *sink) {
   const uint32_t lane = threadIdx.x & 63;
@@ -149,6 +168,19 @@ int wl_fill(void *dev, uint64_t n_bytes, uint64_t seed, uint64_t first_index, vo
   if (rest)
     hipLaunchKernelGGL(fill_tail_kernel, dim3(1), dim3(64), 0, s, base + 8 * words,
                        (uint32_t)rest, host_sm64(seed, first_index / 8 + words));
+  return hipGetLastError() == hipSuccess ? 0 : -9;
+}
+
+// Reference copy of n_rows rows of row16 16-byte vectors (row16 <= 512),
+// row r from src_rows[r] to dst_rows[r] (all 16-byte aligned): one wave per
+// row at a time, every vector of the row loaded before any is stored, no
+// piece table -- what a plain kernel reaches on a scattered-row pattern
+// (measurement only).
+int wl_ref_rows(const void *dst_rows, const void *src_rows, uint32_t n_rows, uint32_t row16,
+                uint32_t blocks, void *stream) {
+  if (!dst_rows || !src_rows || row16 == 0 || row16 > 512 || blocks == 0) return -1;
+  hipLaunchKernelGGL(ref_rows_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                     (const uint64_t *)dst_rows, (const uint64_t *)src_rows, n_rows, row16);
   return hipGetLastError() == hipSuccess ? 0 : -9;
 }
 

@@ -38,6 +38,9 @@ def lib():
         L.wl_ref_copy.restype = ctypes.c_int
         L.wl_ref_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                   ctypes.c_uint32, ctypes.c_void_p]
+        L.wl_ref_rows.restype = ctypes.c_int
+        L.wl_ref_rows.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
         L.wl_ref_stream.restype = ctypes.c_int
         L.wl_ref_stream.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
@@ -56,6 +59,16 @@ def ref_copy(dst: int, src: int, n_bytes: int, blocks: int = 4096, stream: int =
     rc = lib().wl_ref_copy(dst, src, n_bytes, blocks, stream or None)
     if rc != 0:
         raise RuntimeError(f"wl_ref_copy failed ({rc})")
+
+
+def ref_rows(dst_rows: int, src_rows: int, n_rows: int, row_bytes: int, blocks: int,
+             stream: int = 0) -> None:
+    """Plain copy of n_rows rows of row_bytes (a multiple of 16, at most 8 KiB)
+    between the device addresses held in the device arrays dst_rows and
+    src_rows (measurement only)."""
+    rc = lib().wl_ref_rows(dst_rows, src_rows, n_rows, row_bytes // 16, blocks, stream or None)
+    if rc != 0 or row_bytes % 16:
+        raise RuntimeError(f"wl_ref_rows failed ({rc})")
 
 
 REF_COPY, REF_READ, REF_WRITE, REF_MEMCPY = 0, 1, 2, 3
