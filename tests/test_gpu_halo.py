@@ -101,3 +101,34 @@ def test_full_size_sampled_rows(env):
         assert H.hicr_slot_deregister(ctx, int(s)) == H.OK
     del pool
     torch.cuda.empty_cache()
+
+
+def test_reference_rows_kernel_copies_the_rows(env):
+    """The benchmark's plain reference copy of the halo rows (measurement
+    only) moves exactly the bytes the oracle moves, so its rate compares
+    like with like."""
+    torch, H, wd, ctx = env
+    N, Py, Pz, h = 40, 2, 4, 2
+    sb = halo.sub_bytes(N, Py, Pz, h)
+    L = Py * Pz * sb
+    pool = torch.empty(L, dtype=torch.uint8, device="cuda")
+    seed = 7200
+    wd.fill(pool.data_ptr(), L, seed)
+    d = halo.exchange(N, Py, Pz, h)
+    row = int(d["size"][0])
+    base = np.uint64(pool.data_ptr())
+    dst = torch.from_numpy((base + d["dst_slot"].astype(np.uint64) * np.uint64(sb)
+                            + d["dst_off"]).view(np.int64)).to("cuda")
+    src = torch.from_numpy((base + d["src_slot"].astype(np.uint64) * np.uint64(sb)
+                            + d["src_off"]).view(np.int64)).to("cuda")
+    torch.cuda.synchronize()
+    _say("halo reference rows", len(d), row)
+    wd.ref_rows(dst.data_ptr(), src.data_ptr(), len(d), row, 64)
+    torch.cuda.synchronize()
+    host = content(seed, 0, L)
+    oc = oracle.Ctx()
+    ids = np.array([oc.register(host, offset=s * sb, size=sb)[1] for s in range(Py * Pz)])
+    od = d.copy()
+    od["dst_slot"], od["src_slot"] = ids[d["dst_slot"]], ids[d["src_slot"]]
+    assert oc.memcpy_batch(od)[0] == oracle.OK
+    assert np.array_equal(pool.cpu().numpy(), host)
